@@ -1,0 +1,188 @@
+"""FP64 CPU oracle for the sampled GCP gradient -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this package.  It loads ``liboracle.so``, built by gcc from
+``gcp_oracle.c`` in this folder, and shares no code with the HIP library.
+
+Every function here is argument marshalling around the C oracle: the
+arithmetic (Philox draws, sampling, model entries, loss derivatives, the
+sparse MTTKRP and the Adam step) all lives in ``gcp_oracle.c`` and follows
+Kolda & Hong, Alg. 1-4 and eqs. Y, Gks, Fhat, Fhat-strat.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gcp_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+GAUSSIAN, BERNOULLI_ODDS, POISSON = 0, 1, 2
+UNIFORM, STRATIFIED, SEMI_STRATIFIED = 0, 1, 2
+S_UNIFORM, S_NZ, S_ZERO, S_NZ_CORR, S_SEMI_ZERO = 0, 1, 2, 3, 4
+LOSS_EPS = 1e-10
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (plain C, no threads)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = ctypes.CDLL(_LIB_PATH)
+        u64, i64, i32, dbl = ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        P = ctypes.c_void_p
+        L.orc_philox4x64_10.argtypes = [P, P, P]
+        L.orc_philox4x64_10.restype = None
+        L.orc_randi.argtypes = [u64, u64]
+        L.orc_randi.restype = u64
+        L.orc_loss_f.argtypes = [ctypes.c_int, dbl, dbl, dbl]
+        L.orc_loss_f.restype = dbl
+        L.orc_loss_g.argtypes = [ctypes.c_int, dbl, dbl, dbl]
+        L.orc_loss_g.restype = dbl
+        L.orc_sample.argtypes = [ctypes.c_int, ctypes.c_int, P, P, i64, P, P, i64, i64, i64,
+                                 u64, u64, u64, P, P, P, P]
+        L.orc_sample.restype = i64
+        L.orc_grad.argtypes = [ctypes.c_int, ctypes.c_int, P, i64, P, i64, P, P, P,
+                               i64, i64, i64, i64, dbl, P, P]
+        L.orc_grad.restype = dbl
+        L.orc_full_grad.argtypes = [ctypes.c_int, ctypes.c_int, P, i64, P, P, dbl, P]
+        L.orc_full_grad.restype = dbl
+        L.orc_adam.argtypes = [i64, P, P, P, P, i64, dbl, dbl, dbl, dbl, dbl, ctypes.c_int]
+        L.orc_adam.restype = None
+        L.orc_set_mutation.argtypes = [ctypes.c_int]
+        L.orc_set_mutation.restype = None
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def set_mutation(m: int) -> None:
+    """Plant deliberate mistake ``m`` (0 = none); used only by the pin tests."""
+    lib().orc_set_mutation(int(m))
+
+
+def philox4x64_10(key, counter) -> np.ndarray:
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    c = np.ascontiguousarray(counter, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    lib().orc_philox4x64_10(_ptr(k), _ptr(c), _ptr(out))
+    return out
+
+
+def randi(w: int, n: int) -> int:
+    return int(lib().orc_randi(int(w), int(n)))
+
+
+def loss_f(loss: int, x: float, m: float, eps: float = LOSS_EPS) -> float:
+    return lib().orc_loss_f(loss, x, m, eps)
+
+
+def loss_g(loss: int, x: float, m: float, eps: float = LOSS_EPS) -> float:
+    return lib().orc_loss_g(loss, x, m, eps)
+
+
+class Samples:
+    """One sample set: idx [S, d] int64, xval [S] f64, stratum [S] int32, cand [S] int64."""
+
+    def __init__(self, idx, xval, stratum, cand, examined):
+        self.idx, self.xval, self.stratum, self.cand, self.examined = idx, xval, stratum, cand, examined
+
+    def __len__(self):
+        return len(self.xval)
+
+
+def sample(sampler: int, dims, *, dense=None, coo_idx=None, coo_val=None,
+           s: int = 0, p: int = 0, q: int = 0, seed: int = 0, problem_id: int = 0,
+           iteration: int = 0) -> Samples:
+    """Draw one gradient's samples (Alg. 1 / 2 / 3 sampling lines)."""
+    d = len(dims)
+    dims_a = np.ascontiguousarray(dims, dtype=np.int64)
+    S = s if sampler == UNIFORM else p + q
+    idx = np.zeros((max(S, 1), d), dtype=np.int64)
+    xval = np.zeros(max(S, 1), dtype=np.float64)
+    st = np.zeros(max(S, 1), dtype=np.int32)
+    cand = np.zeros(max(S, 1), dtype=np.int64)
+    keep = []
+    if dense is not None:
+        dense_a = np.ascontiguousarray(dense, dtype=np.float64).reshape(-1)
+        keep.append(dense_a)
+        dense_p, nnz, ci_p, cv_p = _ptr(dense_a), 0, None, None
+    else:
+        ci = np.ascontiguousarray(coo_idx, dtype=np.int64).reshape(-1, d)
+        cv = np.ascontiguousarray(coo_val, dtype=np.float64).reshape(-1)
+        keep += [ci, cv]
+        dense_p, nnz, ci_p, cv_p = None, ci.shape[0], _ptr(ci), _ptr(cv)
+    examined = lib().orc_sample(sampler, d, _ptr(dims_a), dense_p, nnz, ci_p, cv_p, s, p, q,
+                                seed, problem_id, iteration, _ptr(idx), _ptr(xval), _ptr(st), _ptr(cand))
+    if examined < 0:
+        raise ValueError("oracle sample: bad arguments")
+    return Samples(idx[:S], xval[:S], st[:S], cand[:S], examined)
+
+
+def _factor_ptrs(A):
+    A64 = [np.ascontiguousarray(a, dtype=np.float64) for a in A]
+    arr = (ctypes.c_void_p * len(A64))(*[a.ctypes.data for a in A64])
+    return A64, arr
+
+
+def grad(loss: int, dims, A, smp: Samples, *, nnz: int = 0, s: int = 0, p: int = 0, q: int = 0,
+         eps: float = LOSS_EPS, want_ytilde: bool = False):
+    """Sampled gradient G_k (list of n_k x r float64) and the loss estimate."""
+    d = len(dims)
+    r = A[0].shape[1]
+    dims_a = np.ascontiguousarray(dims, dtype=np.int64)
+    A64, Ap = _factor_ptrs(A)
+    G = [np.zeros((n, r), dtype=np.float64) for n in dims]
+    Gp = (ctypes.c_void_p * d)(*[g.ctypes.data for g in G])
+    S = len(smp)
+    idx = np.ascontiguousarray(smp.idx, dtype=np.int64).reshape(-1)
+    xv = np.ascontiguousarray(smp.xval, dtype=np.float64)
+    st = np.ascontiguousarray(smp.stratum, dtype=np.int32)
+    yt = np.zeros(max(S, 1), dtype=np.float64)
+    F = lib().orc_grad(loss, d, _ptr(dims_a), r, Ap, S, _ptr(idx), _ptr(xv), _ptr(st),
+                       nnz, s, p, q, eps, _ptr(yt), Gp)
+    if want_ytilde:
+        return G, F, yt[:S]
+    return G, F
+
+
+def full_grad(loss: int, A, dense, eps: float = LOSS_EPS):
+    """Full gradient by enumerating every entry (eqs. Y, Gk); tiny tensors only."""
+    dense_a = np.ascontiguousarray(dense, dtype=np.float64)
+    dims = dense_a.shape
+    d = len(dims)
+    r = A[0].shape[1]
+    dims_a = np.ascontiguousarray(dims, dtype=np.int64)
+    A64, Ap = _factor_ptrs(A)
+    G = [np.zeros((n, r), dtype=np.float64) for n in dims]
+    Gp = (ctypes.c_void_p * d)(*[g.ctypes.data for g in G])
+    F = lib().orc_full_grad(loss, d, _ptr(dims_a), r, Ap, _ptr(dense_a.reshape(-1)), eps, Gp)
+    return G, F
+
+
+def adam(A, G, B, C, t: int, alpha=0.01, beta1=0.9, beta2=0.999, eps=1e-8,
+         lower=-np.inf, eps_mode: int = 0):
+    """One Adam step (Alg. 4) in place on flat float64 arrays A, B, C; t >= 1."""
+    for a in (A, B, C):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    G64 = np.ascontiguousarray(G, dtype=np.float64)
+    lib().orc_adam(A.size, _ptr(A), _ptr(G64), _ptr(B), _ptr(C), int(t), alpha, beta1, beta2,
+                   eps, lower, eps_mode)

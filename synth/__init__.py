@@ -1,0 +1,297 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module only makes inputs: data tensors, true factors and starting
+factors.  It holds none of the sampled-gradient arithmetic (no sampling, no
+loss derivative, no MTTKRP, no Adam); both the HIP path and the oracle consume
+what it returns.  Every array comes from numpy's PCG64 with a fixed seed and a
+fixed traversal order, so the same call gives the same bytes on any machine.
+
+Workloads (dims, rank, loss, sampler; data recipe):
+
+* ``dense_gaussian_30x40x50`` -- 30x40x50, rank 4, FP64.  X = [[A1,A2,A3]] with
+  N(0,1) factor entries plus 0.1*N(0,1) noise; Gaussian loss; uniform sampling,
+  s = 2000; evaluated at an independent N(0,1) start.
+* ``sparse_binary_1000x800x600`` -- binary, rank 8, FP32.  Factor entries
+  U(0,1); the model is scaled by lambda so that the mean odds-probability
+  lambda*m/(1+lambda*m) is 0.002; every entry is drawn Bernoulli(lambda*m/(1+lambda*m))
+  (the odds link of the paper's binary recipe).  Bernoulli-odds loss,
+  stratified sampling p = q = 1e5.
+* ``sparse_count_6000x24x77x32`` -- counts, rank 10, FP32.  Factor entries
+  Gamma(0.5, 1); the model is scaled so that the expected number of nonzeros
+  sum(1 - exp(-lambda*m)) is 5e6; entries are Poisson(lambda*m).  Poisson loss,
+  semi-stratified sampling p = q = 5e5.  Stands in for the Chicago crime
+  tensor (6186x24x77x32, 5.3M nonzeros, rank 10), which is not available.
+
+Seeds: data 1000c+1, start 1000c+2, samples 1000c+3 for workload c = 1, 2, 3.
+"""
+from __future__ import annotations
+
+import dataclasses
+import hashlib
+import os
+from typing import List, Optional
+
+import numpy as np
+
+GAUSSIAN, BERNOULLI_ODDS, POISSON = 0, 1, 2
+UNIFORM, STRATIFIED, SEMI_STRATIFIED = 0, 1, 2
+
+_CACHE = os.environ.get("GCP_DATA_CACHE",
+                        os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                                     "data_cache"))
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    dims: tuple
+    rank: int
+    loss: int
+    sampler: int
+    dtype: str                       # factor storage: "f64", "f32" or "bf16"
+    s: int = 0                       # uniform samples
+    p: int = 0                       # nonzero samples
+    q: int = 0                       # zero samples
+    dense: Optional[np.ndarray] = None        # row-major dense X
+    coo_idx: Optional[np.ndarray] = None      # [nnz, d] uint32, sorted by row-major linear index
+    coo_val: Optional[np.ndarray] = None      # [nnz]
+    A_true: Optional[List[np.ndarray]] = None
+    A_init: Optional[List[np.ndarray]] = None
+    seed: int = 0                    # sample stream seed
+    lower: float = -np.inf           # projection bound of the Adam step
+    lr: float = 0.01
+
+    @property
+    def d(self) -> int:
+        return len(self.dims)
+
+    @property
+    def nnz(self) -> int:
+        return 0 if self.coo_idx is None else int(self.coo_idx.shape[0])
+
+    @property
+    def omega(self) -> int:
+        return int(np.prod(np.array(self.dims, dtype=object)))
+
+    @property
+    def n_samples(self) -> int:
+        return self.s if self.sampler == UNIFORM else self.p + self.q
+
+
+# ---------------------------------------------------------------------------
+# small building blocks
+# ---------------------------------------------------------------------------
+
+def _full(A: List[np.ndarray]) -> np.ndarray:
+    """Dense tensor of a CP model (data construction only)."""
+    d = len(A)
+    letters = "abcdefgh"[:d]
+    spec = ",".join(f"{c}z" for c in letters) + "->" + letters
+    return np.einsum(spec, *A, optimize=True)
+
+
+def dense_gaussian(dims, rank, seed, noise=0.1, dtype=np.float64):
+    """X = [[A_1..A_d]] + noise*N(0,1), factors N(0,1); returns (X, A_true)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    A = [rng.standard_normal((n, rank)) for n in dims]
+    X = _full(A) + noise * rng.standard_normal(tuple(dims))
+    return X.astype(dtype), [a.astype(dtype) for a in A]
+
+
+def gaussian_start(dims, rank, seed, dtype=np.float64):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return [rng.standard_normal((n, rank)).astype(dtype) for n in dims]
+
+
+def _slab_models(A, lam):
+    """Yield (slab index, lambda * model values of that mode-0 slab)."""
+    rest = A[1:]
+    for i0 in range(A[0].shape[0]):
+        B = [rest[0] * A[0][i0]] + rest[1:]
+        yield i0, lam * _full(B)
+
+
+def _subsample_models(A, count, rng):
+    idx = [rng.integers(0, a.shape[0], size=count) for a in A]
+    prod = np.ones((count, A[0].shape[1]))
+    for k, a in enumerate(A):
+        prod *= a[idx[k]]
+    return prod.sum(axis=1)
+
+
+def _bisect_scale(target, func, lo=1e-12, hi=1e12, iters=200):
+    """Scale lambda (geometric bisection) with func(lambda) = target, func increasing."""
+    for _ in range(iters):
+        mid = np.sqrt(lo * hi)
+        if func(mid) < target:
+            lo = mid
+        else:
+            hi = mid
+    return np.sqrt(lo * hi)
+
+
+def sparse_binary(dims, rank, density, seed, subsample=2_000_000):
+    """Binary tensor, entries Bernoulli(lam*m/(1+lam*m)); factors U(0,1).
+
+    lambda is chosen on a seeded subsample of entries so that the mean
+    probability is ``density``; factors are returned scaled by lambda^(1/d).
+    Returns (coo_idx uint32 [nnz, d], coo_val float64 ones, A_true, lambda^(1/d)).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d = len(dims)
+    A = [rng.random((n, rank)) for n in dims]
+    msub = _subsample_models(A, subsample, rng)
+    lam = _bisect_scale(density, lambda l: float(np.mean(l * msub / (1.0 + l * msub))))
+    coords = []
+    for i0, m in _slab_models(A, lam):
+        u = rng.random(m.shape)
+        hit = np.nonzero(u < m / (1.0 + m))
+        if hit[0].size:
+            c = np.empty((hit[0].size, d), dtype=np.uint32)
+            c[:, 0] = i0
+            for k in range(1, d):
+                c[:, k] = hit[k - 1]
+            coords.append(c)
+    coo = np.concatenate(coords) if coords else np.zeros((0, d), dtype=np.uint32)
+    scale = lam ** (1.0 / d)
+    return coo, np.ones(coo.shape[0]), [a * scale for a in A], scale
+
+
+def _poisson_inverse_cdf(mu, v):
+    """Smallest k >= 1 with CDF_Poisson(mu)(k) >= v, for v > exp(-mu) (vectorised)."""
+    pmf = np.exp(-mu)
+    cdf = pmf.copy()
+    k = np.zeros(mu.shape, dtype=np.int64)
+    todo = np.ones(mu.shape, dtype=bool)
+    while todo.any():
+        k[todo] += 1
+        pmf[todo] = pmf[todo] * mu[todo] / k[todo]
+        cdf[todo] += pmf[todo]
+        todo &= cdf < v
+        todo &= k < 10_000
+    return k
+
+
+def sparse_counts(dims, rank, nnz_target, seed, subsample=2_000_000):
+    """Count tensor, entries Poisson(lam*m); factors Gamma(0.5, 1).
+
+    lambda is chosen on a seeded subsample so that the expected number of
+    nonzeros sum(1 - exp(-lam*m)) is ``nnz_target``.  Each entry uses one
+    uniform v: it is zero when v <= exp(-lam*m), else the Poisson inverse CDF
+    at v.  Returns (coo_idx uint32 [nnz, d], coo_val float64, A_true scaled
+    by lambda^(1/d), lambda^(1/d)).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d = len(dims)
+    A = [rng.gamma(0.5, 1.0, size=(n, rank)) for n in dims]
+    omega = float(np.prod(np.array(dims, dtype=np.float64)))
+    msub = _subsample_models(A, subsample, rng)
+    lam = _bisect_scale(nnz_target / omega, lambda l: float(np.mean(-np.expm1(-l * msub))))
+    coords, vals = [], []
+    for i0, m in _slab_models(A, lam):
+        v = rng.random(m.shape)
+        hit = np.nonzero(v > np.exp(-m))
+        if hit[0].size:
+            c = np.empty((hit[0].size, d), dtype=np.uint32)
+            c[:, 0] = i0
+            for k in range(1, d):
+                c[:, k] = hit[k - 1]
+            coords.append(c)
+            vals.append(_poisson_inverse_cdf(m[hit], v[hit]).astype(np.float64))
+    coo = np.concatenate(coords) if coords else np.zeros((0, d), dtype=np.uint32)
+    val = np.concatenate(vals) if vals else np.zeros(0)
+    scale = lam ** (1.0 / d)
+    return coo, val, [a * scale for a in A], scale
+
+
+def nonneg_start(dims, rank, seed, kind, scale):
+    """Positive start: same distribution and scale as the true factors, new seed."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if kind == "uniform":
+        return [rng.random((n, rank)) * scale for n in dims]
+    return [rng.gamma(0.5, 1.0, size=(n, rank)) * scale for n in dims]
+
+
+# ---------------------------------------------------------------------------
+# cache (numpy .npz, no pickles)
+# ---------------------------------------------------------------------------
+
+def _cached(key: str, make):
+    os.makedirs(_CACHE, exist_ok=True)
+    h = hashlib.sha1(key.encode()).hexdigest()[:16]
+    path = os.path.join(_CACHE, f"{h}.npz")
+    if os.path.exists(path):
+        with np.load(path, allow_pickle=False) as z:
+            return {k: z[k] for k in z.files}
+    out = make()
+    tmp = path + f".tmp{os.getpid()}.npz"
+    np.savez(tmp, **out)
+    os.replace(tmp, path)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# the workloads
+# ---------------------------------------------------------------------------
+
+def dense_gaussian_30x40x50() -> Workload:
+    dims, r = (30, 40, 50), 4
+    X, A_true = dense_gaussian(dims, r, seed=1001)
+    A0 = gaussian_start(dims, r, seed=1002)
+    return Workload("dense_gaussian_30x40x50", dims, r, GAUSSIAN, UNIFORM, "f64", s=2000,
+                    dense=X, A_true=A_true, A_init=A0, seed=1003, lr=1e-3)
+
+
+def sparse_binary_workload(dims=(1000, 800, 600), rank=8, density=0.002, p=100_000, q=100_000,
+                           seed_base=2000, name=None, cache=True) -> Workload:
+    d = len(dims)
+
+    def make():
+        coo, val, A_true, scale = sparse_binary(dims, rank, density, seed=seed_base + 1)
+        out = {"coo": coo, "val": val, "scale": np.array(scale)}
+        for k, a in enumerate(A_true):
+            out[f"A{k}"] = a
+        return out
+
+    key = f"sparse_binary:{dims}:{rank}:{density}:{seed_base}:v2"
+    z = _cached(key, make) if cache else make()
+    A_true = [z[f"A{k}"] for k in range(d)]
+    A0 = nonneg_start(dims, rank, seed_base + 2, "uniform", float(z["scale"]))
+    return Workload(name or f"sparse_binary_{'x'.join(map(str, dims))}", tuple(dims), rank,
+                    BERNOULLI_ODDS, STRATIFIED, "f32", p=p, q=q, coo_idx=z["coo"],
+                    coo_val=z["val"], A_true=A_true, A_init=A0, seed=seed_base + 3, lower=0.0)
+
+
+def sparse_count_workload(dims=(6000, 24, 77, 32), rank=10, nnz_target=5.0e6, p=500_000,
+                          q=500_000, seed_base=3000, name=None, cache=True) -> Workload:
+    d = len(dims)
+
+    def make():
+        coo, val, A_true, scale = sparse_counts(dims, rank, nnz_target, seed=seed_base + 1)
+        out = {"coo": coo, "val": val, "scale": np.array(scale)}
+        for k, a in enumerate(A_true):
+            out[f"A{k}"] = a
+        return out
+
+    key = f"sparse_counts:{dims}:{rank}:{nnz_target}:{seed_base}:v2"
+    z = _cached(key, make) if cache else make()
+    A_true = [z[f"A{k}"] for k in range(d)]
+    A0 = nonneg_start(dims, rank, seed_base + 2, "gamma", float(z["scale"]))
+    return Workload(name or f"sparse_count_{'x'.join(map(str, dims))}", tuple(dims), rank,
+                    POISSON, SEMI_STRATIFIED, "f32", p=p, q=q, coo_idx=z["coo"], coo_val=z["val"],
+                    A_true=A_true, A_init=A0, seed=seed_base + 3, lower=0.0)
+
+
+def sparse_binary_1000x800x600() -> Workload:
+    return sparse_binary_workload()
+
+
+def sparse_count_6000x24x77x32() -> Workload:
+    return sparse_count_workload()
+
+
+WORKLOADS = {
+    "dense_gaussian_30x40x50": dense_gaussian_30x40x50,
+    "sparse_binary_1000x800x600": sparse_binary_1000x800x600,
+    "sparse_count_6000x24x77x32": sparse_count_6000x24x77x32,
+}

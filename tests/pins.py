@@ -1,0 +1,469 @@
+"""Independent checks ("pins") for the FP64 oracle.
+
+Each ``pin_*`` function computes something the paper or the mathematics fixes
+by a route other than the oracle's own code, compares, and returns
+``(ok, detail)``.  ``tests/test_oracle_pins.py`` asserts every pin holds;
+``tests/test_oracle_mutations.py`` plants each deliberate mistake in the oracle
+and asserts that at least one pin catches it.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.special
+import scipy.stats
+
+import oracle
+import synth
+
+MASK64 = (1 << 64) - 1
+
+
+# ---------------------------------------------------------------------------
+# independent re-derivations
+# ---------------------------------------------------------------------------
+
+def numpy_philox_block(key, counter):
+    """Philox4x64-10 block at ``counter`` via numpy (which increments first)."""
+    c = [int(x) for x in counter]
+    pred = (c[0] | (c[1] << 64) | (c[2] << 128) | (c[3] << 192)) - 1
+    pred &= (1 << 256) - 1
+    words = np.array([(pred >> (64 * t)) & MASK64 for t in range(4)], dtype=np.uint64)
+    bg = np.random.Philox(key=np.array([int(key[0]), int(key[1])], dtype=np.uint64), counter=words)
+    return bg.random_raw(4)
+
+
+def numpy_index(seed, pid, j, iteration, purpose, dims):
+    """Mode indices of draw j: word k -> floor(w_k * n_k / 2^64), exact integers."""
+    out = []
+    blocks = {}
+    for k, n in enumerate(dims):
+        b = k // 4
+        if b not in blocks:
+            blocks[b] = numpy_philox_block((seed, pid), (j, iteration, purpose, b))
+        w = int(blocks[b][k % 4])
+        out.append((w * int(n)) >> 64)
+    return tuple(out)
+
+
+def khatri_rao(mats):
+    """Column-wise Kronecker product; the first matrix varies slowest."""
+    out = mats[0]
+    for m in mats[1:]:
+        out = (out[:, None, :] * m[None, :, :]).reshape(-1, out.shape[1])
+    return out
+
+
+def unfold(T, k):
+    """Mode-k unfolding; remaining modes in order, last fastest (row-major)."""
+    return np.moveaxis(T, k, 0).reshape(T.shape[k], -1)
+
+
+def full_model(A):
+    d = len(A)
+    letters = "abcdefgh"[:d]
+    return np.einsum(",".join(f"{c}z" for c in letters) + "->" + letters, *A)
+
+
+def exact_gradient(loss, X, A, eps=oracle.LOSS_EPS):
+    """G_k = Y_(k) Z_k (eqs. Y, Gk) with explicit unfolding and Khatri-Rao product."""
+    M = full_model(A)
+    gvec = np.vectorize(lambda x, m: oracle.loss_g(loss, float(x), float(m), eps))
+    Y = gvec(X, M)
+    G = []
+    for k in range(len(A)):
+        Z = khatri_rao([A[j] for j in range(len(A)) if j != k])
+        G.append(unfold(Y, k) @ Z)
+    return G
+
+
+def enumeration_samples(dims, X):
+    """Every index once, uniform stratum, in row-major order (s = number of entries)."""
+    grids = np.meshgrid(*[np.arange(n) for n in dims], indexing="ij")
+    idx = np.stack([g.reshape(-1) for g in grids], axis=1).astype(np.int64)
+    S = idx.shape[0]
+    return oracle.Samples(idx, np.asarray(X, dtype=np.float64).reshape(-1),
+                          np.zeros(S, dtype=np.int32), np.arange(S), S)
+
+
+def rel_err(a_list, b_list):
+    num = sum(float(np.sum((np.asarray(a) - np.asarray(b)) ** 2)) for a, b in zip(a_list, b_list))
+    den = sum(float(np.sum(np.asarray(b) ** 2)) for b in b_list)
+    return math.sqrt(num / max(den, 1e-300))
+
+
+# ---------------------------------------------------------------------------
+# tiny test problems
+# ---------------------------------------------------------------------------
+
+def tiny_dense(dims=(3, 4, 5), r=3, seed=11):
+    X, _ = synth.dense_gaussian(dims, r, seed=seed)
+    A = synth.gaussian_start(dims, r, seed=seed + 1)
+    return X, A
+
+
+def tiny_sparse(kind, dims=(6, 5, 4), r=3, seed=21):
+    """Tiny binary or count tensor, its dense form, COO and a positive start."""
+    if kind == "binary":
+        coo, val, A_true, scale = synth.sparse_binary(dims, r, 0.2, seed=seed, subsample=20000)
+        A = synth.nonneg_start(dims, r, seed + 1, "uniform", scale)
+    else:
+        omega = int(np.prod(dims))
+        coo, val, A_true, scale = synth.sparse_counts(dims, r, 0.25 * omega, seed=seed, subsample=20000)
+        A = synth.nonneg_start(dims, r, seed + 1, "gamma", scale)
+    X = np.zeros(dims)
+    for e in range(coo.shape[0]):
+        X[tuple(int(t) for t in coo[e])] = val[e]
+    return X, coo.astype(np.int64), val, A
+
+
+# ---------------------------------------------------------------------------
+# pins
+# ---------------------------------------------------------------------------
+
+def pin_philox_numpy(n=200, seed=5):
+    """P0: oracle Philox4x64-10 == numpy.random.Philox on many keys/counters."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cases = [((0, 0), (0, 0, 0, 0)), ((MASK64, MASK64), (MASK64, MASK64, MASK64, MASK64)),
+             ((1, 2), (MASK64, 0, 0, 0)), ((3, 4), (0, MASK64, 7, 1))]
+    for _ in range(n):
+        cases.append((tuple(int(x) for x in rng.integers(0, 2**63, 2, dtype=np.int64)),
+                      tuple(int(x) for x in rng.integers(0, 2**63, 4, dtype=np.int64))))
+    for key, ctr in cases:
+        a = oracle.philox4x64_10(key, ctr)
+        b = numpy_philox_block(key, ctr)
+        if not np.array_equal(a, b):
+            return False, f"key={key} ctr={ctr}: {a} != {b}"
+    return True, f"{len(cases)} blocks"
+
+
+def pin_randi_exact(n=2000, seed=6):
+    """randi(n) == floor(w n / 2^64) in exact integer arithmetic, in range."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ws = [0, 1, MASK64, 1 << 63] + [int(x) * 2 + 1 for x in rng.integers(0, 2**63, n, dtype=np.int64)]
+    ns = [1, 2, 3, 1000, 959756, 2**32 + 15, 2**63 - 25]
+    for w in ws:
+        for m in ns:
+            got = oracle.randi(w, m)
+            if got != (w * m) >> 64 or not (0 <= got < m):
+                return False, f"w={w} n={m}: {got}"
+    return True, "ok"
+
+
+def pin_sample_streams(iteration=3, seed=77, pid=2):
+    """Sample indices == the counter contract recomputed with numpy's Philox.
+
+    Uniform (purpose 0), nonzero picks (purpose 1, xi = randi(eta)), stratified
+    rejection (purpose 2, first q non-members in counter order) and semi
+    "zeros" (purpose 0, no rejection) -- Alg. 1, 2, 3 sampling lines.
+    """
+    X, coo, val, _ = tiny_sparse("binary")
+    dims = X.shape
+    nz = {tuple(int(t) for t in c) for c in coo}
+    eta = coo.shape[0]
+    # uniform on the dense form
+    smp = oracle.sample(oracle.UNIFORM, dims, dense=X, s=40, seed=seed, problem_id=pid, iteration=iteration)
+    for c in range(40):
+        ii = numpy_index(seed, pid, c, iteration, 0, dims)
+        if tuple(smp.idx[c]) != ii or smp.xval[c] != X[ii]:
+            return False, f"uniform sample {c}: {tuple(smp.idx[c])} vs {ii}"
+    # stratified
+    p, q = 15, 25
+    smp = oracle.sample(oracle.STRATIFIED, dims, coo_idx=coo, coo_val=val, p=p, q=q, seed=seed,
+                        problem_id=pid, iteration=iteration)
+    for c in range(p):
+        w = int(numpy_philox_block((seed, pid), (c, iteration, 1, 0))[0])
+        e = (w * eta) >> 64
+        if tuple(smp.idx[c]) != tuple(int(t) for t in coo[e]) or smp.stratum[c] != oracle.S_NZ:
+            return False, f"nonzero pick {c}"
+    accepted, j = [], 0
+    while len(accepted) < q:
+        ii = numpy_index(seed, pid, j, iteration, 2, dims)
+        if ii not in nz:
+            accepted.append((j, ii))
+        j += 1
+    if smp.examined != j:
+        return False, f"candidates examined {smp.examined} != {j}"
+    for c, (jj, ii) in enumerate(accepted):
+        o = p + c
+        if tuple(smp.idx[o]) != ii or smp.cand[o] != jj or smp.xval[o] != 0.0 or smp.stratum[o] != oracle.S_ZERO:
+            return False, f"zero sample {c}: oracle {tuple(smp.idx[o])}@{smp.cand[o]} vs {ii}@{jj}"
+    # semi-stratified
+    smp = oracle.sample(oracle.SEMI_STRATIFIED, dims, coo_idx=coo, coo_val=val, p=p, q=q, seed=seed,
+                        problem_id=pid, iteration=iteration)
+    for c in range(q):
+        ii = numpy_index(seed, pid, c, iteration, 0, dims)
+        o = p + c
+        if tuple(smp.idx[o]) != ii or smp.xval[o] != 0.0 or smp.stratum[o] != oracle.S_SEMI_ZERO:
+            return False, f"semi zero {c}"
+    for c in range(p):
+        if smp.stratum[c] != oracle.S_NZ_CORR:
+            return False, "semi nonzero stratum"
+    return True, "ok"
+
+
+def pin_stratified_zeros_are_zeros():
+    """P5: stratified zero samples never hit a nonzero; x = 0 there."""
+    X, coo, val, _ = tiny_sparse("binary")
+    for it in range(20):
+        smp = oracle.sample(oracle.STRATIFIED, X.shape, coo_idx=coo, coo_val=val, p=5, q=60,
+                            seed=9, iteration=it)
+        for o in range(5, 65):
+            if X[tuple(smp.idx[o])] != 0.0:
+                return False, f"iteration {it}: zero sample {o} hit a nonzero"
+    return True, "ok"
+
+
+def pin_index_uniformity(seed=1234):
+    """P5: per-mode histograms of uniform draws pass a chi-square test; E[count] = s/n."""
+    dims = (7, 11, 5)
+    X = np.zeros(dims)
+    smp = oracle.sample(oracle.UNIFORM, dims, dense=X, s=20000, seed=seed)
+    for k, n in enumerate(dims):
+        h = np.bincount(smp.idx[:, k], minlength=n)
+        pval = scipy.stats.chisquare(h).pvalue
+        if pval < 1e-4:
+            return False, f"mode {k} chi-square p={pval}"
+    lin = np.ravel_multi_index(tuple(smp.idx.T), dims)
+    h = np.bincount(lin, minlength=int(np.prod(dims)))
+    pval = scipy.stats.chisquare(h).pvalue
+    if pval < 1e-4:
+        return False, f"joint chi-square p={pval}"
+    return True, "ok"
+
+
+def pin_enumeration_equals_unfolding(losses=(oracle.GAUSSIAN, oracle.BERNOULLI_ODDS, oracle.POISSON)):
+    """P1: the sampled gradient over every index once (weight omega/s = 1) equals
+    Y_(k) Z_k computed by explicit unfolding and Khatri-Rao products (eq. Gk)."""
+    for dims in [(3, 4, 5), (2, 3, 4, 5)]:
+        for loss in losses:
+            if loss == oracle.GAUSSIAN:
+                X, A = tiny_dense(dims)
+            else:
+                X, _ = tiny_dense(dims)
+                X = (np.abs(X) > 1.0).astype(float) if loss == oracle.BERNOULLI_ODDS else np.round(np.abs(X))
+                A = [np.abs(a) + 0.1 for a in synth.gaussian_start(dims, 3, seed=5)]
+            smp = enumeration_samples(dims, X)
+            G, _ = oracle.grad(loss, dims, A, smp, s=len(smp))
+            Gx = exact_gradient(loss, X, A)
+            e = rel_err(G, Gx)
+            if e > 1e-12:
+                return False, f"dims={dims} loss={loss}: rel err {e:.3e}"
+            Gf, _ = oracle.full_grad(loss, A, X)
+            e = rel_err(Gf, Gx)
+            if e > 1e-12:
+                return False, f"full_grad dims={dims} loss={loss}: rel err {e:.3e}"
+    return True, "ok"
+
+
+def pin_gaussian_closed_form():
+    """P2: Gaussian (standard CP) gradient in closed form (App. A):
+    G_k = 2 (A_k (hadamard_{j != k} A_j^T A_j) - X_(k) Z_k), on the 30x40x50 workload."""
+    w = synth.dense_gaussian_30x40x50()
+    A, X = w.A_init, w.dense
+    smp = enumeration_samples(w.dims, X)
+    G, _ = oracle.grad(oracle.GAUSSIAN, w.dims, A, smp, s=len(smp))
+    Gc = []
+    for k in range(w.d):
+        others = [A[j] for j in range(w.d) if j != k]
+        gram = np.ones((w.rank, w.rank))
+        for a in others:
+            gram *= a.T @ a
+        Gc.append(2.0 * (A[k] @ gram - unfold(X, k) @ khatri_rao(others)))
+    e = rel_err(G, Gc)
+    return e <= 1e-10, f"rel err {e:.3e}"
+
+
+def pin_poisson_closed_form():
+    """P3: Poisson gradient in closed form (App. A): G_k = 1 (hadamard_{j != k} 1^T A_j)
+    - V_(k) Z_k with v = x / (m + eps) on the nonzeros only."""
+    X, coo, val, A = tiny_sparse("counts", dims=(7, 6, 5, 4), r=3)
+    dims = X.shape
+    smp = enumeration_samples(dims, X)
+    G, _ = oracle.grad(oracle.POISSON, dims, A, smp, s=len(smp))
+    M = full_model(A)
+    V = np.where(X != 0, X / (M + oracle.LOSS_EPS), 0.0)
+    Gc = []
+    for k in range(len(dims)):
+        others = [A[j] for j in range(len(dims)) if j != k]
+        colsum = np.ones(A[0].shape[1])
+        for a in others:
+            colsum = colsum * a.sum(axis=0)
+        Gc.append(np.outer(np.ones(dims[k]), colsum) - unfold(V, k) @ khatri_rao(others))
+    e = rel_err(G, Gc)
+    return e <= 1e-11, f"rel err {e:.3e}"
+
+
+def pin_loss_likelihoods():
+    """Losses from their likelihoods: Bernoulli with odds m has P(x=1) = m/(1+m);
+    Poisson f = -log pmf(x; m) - log x!; Gaussian f = (x - m)^2.  Derivatives by
+    central differences of f."""
+    for m in [0.01, 0.3, 1.0, 4.5]:
+        if abs(oracle.loss_f(oracle.BERNOULLI_ODDS, 1.0, m, 0.0) + math.log(m / (1 + m))) > 1e-12:
+            return False, "bernoulli x=1"
+        if abs(oracle.loss_f(oracle.BERNOULLI_ODDS, 0.0, m, 0.0) + math.log(1 / (1 + m))) > 1e-12:
+            return False, "bernoulli x=0"
+        for x in [0, 1, 3, 7]:
+            ref = -scipy.stats.poisson.logpmf(x, m) - scipy.special.gammaln(x + 1)
+            if abs(oracle.loss_f(oracle.POISSON, float(x), m, 0.0) - ref) > 1e-10 * max(1, abs(ref)):
+                return False, f"poisson x={x} m={m}"
+        for x in [-1.5, 0.0, 2.0]:
+            if abs(oracle.loss_f(oracle.GAUSSIAN, x, m, 0.0) - (x - m) ** 2) > 1e-14:
+                return False, "gaussian"
+    for loss in (oracle.GAUSSIAN, oracle.BERNOULLI_ODDS, oracle.POISSON):
+        for x in [0.0, 1.0, 2.0]:
+            for m in [0.2, 1.3, 3.0]:
+                h = 1e-5
+                fd = (oracle.loss_f(loss, x, m + h) - oracle.loss_f(loss, x, m - h)) / (2 * h)
+                g = oracle.loss_g(loss, x, m)
+                if abs(fd - g) > 1e-7 * max(1.0, abs(g)):
+                    return False, f"derivative loss={loss} x={x} m={m}: {g} vs fd {fd}"
+    return True, "ok"
+
+
+def _mean_and_trace(draw, N):
+    vals = [np.concatenate([g.reshape(-1) for g in draw(t)]) for t in range(N)]
+    V = np.stack(vals)
+    return V.mean(axis=0), float(V.var(axis=0, ddof=1).sum())
+
+
+def pin_unbiased(sampler, loss, N=2000):
+    """P4: mean of N sampled gradients -> exact gradient; ||mean - g||^2 <= 3 tr(Sigma)/N
+    (E||mean - g||^2 = tr(Sigma)/N), for the three samplers (Sec. 4.1-4.3)."""
+    if sampler == oracle.UNIFORM:
+        X, A = tiny_dense((4, 3, 5), r=2)
+        coo = val = None
+        nnz = 0
+    else:
+        X, coo, val, A = tiny_sparse("binary" if loss == oracle.BERNOULLI_ODDS else "counts")
+        nnz = coo.shape[0]
+    dims = X.shape
+    Gx = np.concatenate([g.reshape(-1) for g in exact_gradient(loss, X, A)])
+    s, p, q = 12, 6, 8
+
+    def draw(t):
+        if sampler == oracle.UNIFORM:
+            smp = oracle.sample(sampler, dims, dense=X, s=s, seed=31, iteration=t)
+        else:
+            smp = oracle.sample(sampler, dims, coo_idx=coo, coo_val=val, p=p, q=q, seed=31, iteration=t)
+        G, _ = oracle.grad(loss, dims, A, smp, nnz=nnz, s=s, p=p, q=q)
+        return G
+
+    mean, tr = _mean_and_trace(draw, N)
+    dev = float(np.sum((mean - Gx) ** 2))
+    return dev <= 3.0 * tr / N, f"||mean-g||^2={dev:.4g} bound={3.0 * tr / N:.4g}"
+
+
+def pin_semi_zero_half_poisson(N=2000):
+    """P6: with p = 0 the semi-stratified estimate for Poisson (g(0,m) = 1) has
+    expectation the all-ones MTTKRP, 1 (hadamard_{j != k} 1^T A_j)."""
+    X, coo, val, A = tiny_sparse("counts")
+    dims = X.shape
+    r = A[0].shape[1]
+    want = []
+    for k in range(len(dims)):
+        colsum = np.ones(r)
+        for j in range(len(dims)):
+            if j != k:
+                colsum = colsum * A[j].sum(axis=0)
+        want.append(np.outer(np.ones(dims[k]), colsum))
+    Gx = np.concatenate([g.reshape(-1) for g in want])
+
+    def draw(t):
+        smp = oracle.sample(oracle.SEMI_STRATIFIED, dims, coo_idx=coo, coo_val=val, p=0, q=10, seed=8,
+                            iteration=t)
+        G, _ = oracle.grad(oracle.POISSON, dims, A, smp, nnz=coo.shape[0], p=0, q=10)
+        return G
+
+    mean, tr = _mean_and_trace(draw, N)
+    dev = float(np.sum((mean - Gx) ** 2))
+    return dev <= 3.0 * tr / N, f"||mean-g||^2={dev:.4g} bound={3.0 * tr / N:.4g}"
+
+
+def pin_adam_closed_forms():
+    """P7: first step (t = 1) gives Bhat = G, Chat = G^2, so dA = -alpha G / sqrt(G^2 + eps)
+    (eps inside the root, Alg. 4) or -alpha G / (|G| + eps); a constant gradient keeps
+    Bhat = G and Chat = G^2 at every t (bias correction); G = 0 leaves A; projection clamps."""
+    rng = np.random.Generator(np.random.PCG64(3))
+    P = 257
+    G = rng.standard_normal(P) * 10.0 ** rng.uniform(-6, 2, P)
+    G[:5] = 0.0
+    alpha, eps = 0.01, 1e-8
+    for mode in (0, 1):
+        A = rng.standard_normal(P)
+        A0 = A.copy()
+        B = np.zeros(P)
+        C = np.zeros(P)
+        for t in range(1, 6):
+            oracle.adam(A, G, B, C, t, alpha=alpha, eps=eps, eps_mode=mode)
+            den = np.sqrt(G * G + eps) if mode == 0 else np.abs(G) + eps
+            expect = A0 - t * alpha * G / den
+            err = np.max(np.abs(A - expect) / (1 + np.abs(expect)))
+            if err > 1e-12:
+                return False, f"eps_mode={mode} t={t}: err {err:.3e}"
+        if not np.array_equal(A[:5], A0[:5]):
+            return False, "zero-gradient entries moved"
+    A = np.full(P, 0.001)
+    B = np.zeros(P)
+    C = np.zeros(P)
+    oracle.adam(A, np.abs(G) + 1.0, B, C, 1, alpha=alpha, eps=eps, lower=0.0)
+    if not (np.all(A >= 0.0) and np.any(A == 0.0)):
+        return False, "projection"
+    return True, "ok"
+
+
+def pin_finite_differences(loss, h=None):
+    """P8: the sampled gradient is the exact gradient of the sampled loss estimate on
+    a fixed sample set (eqs. Fhat, Fhat-strat); central differences in single
+    coordinates (the model is linear in each, so Gaussian differences are exact)."""
+    if loss == oracle.GAUSSIAN:
+        X, A = tiny_dense((4, 3, 5), r=3)
+        dims = X.shape
+        smp = oracle.sample(oracle.UNIFORM, dims, dense=X, s=30, seed=4)
+        kw = dict(s=30)
+        h = h or 1e-3
+    else:
+        X, coo, val, A = tiny_sparse("binary" if loss == oracle.BERNOULLI_ODDS else "counts")
+        dims = X.shape
+        sampler = oracle.STRATIFIED if loss == oracle.BERNOULLI_ODDS else oracle.SEMI_STRATIFIED
+        smp = oracle.sample(sampler, dims, coo_idx=coo, coo_val=val, p=9, q=11, seed=4)
+        kw = dict(nnz=coo.shape[0], p=9, q=11)
+        h = h or 1e-6
+    G, _ = oracle.grad(loss, dims, A, smp, **kw)
+    worst = 0.0
+    for k in range(len(dims)):
+        for i in range(dims[k]):
+            for j in range(A[0].shape[1]):
+                Ap = [a.copy() for a in A]
+                Am = [a.copy() for a in A]
+                Ap[k][i, j] += h
+                Am[k][i, j] -= h
+                _, fp = oracle.grad(loss, dims, Ap, smp, **kw)
+                _, fm = oracle.grad(loss, dims, Am, smp, **kw)
+                fd = (fp - fm) / (2 * h)
+                worst = max(worst, abs(fd - G[k][i, j]) / max(1.0, abs(G[k][i, j])))
+    tol = 1e-8 if loss == oracle.GAUSSIAN else 1e-5
+    return worst <= tol, f"worst rel {worst:.3e}"
+
+
+ALL_PINS = {
+    "philox_numpy": pin_philox_numpy,
+    "randi_exact": pin_randi_exact,
+    "sample_streams": pin_sample_streams,
+    "stratified_zeros_are_zeros": pin_stratified_zeros_are_zeros,
+    "index_uniformity": pin_index_uniformity,
+    "enumeration_equals_unfolding": pin_enumeration_equals_unfolding,
+    "gaussian_closed_form": pin_gaussian_closed_form,
+    "poisson_closed_form": pin_poisson_closed_form,
+    "loss_likelihoods": pin_loss_likelihoods,
+    "unbiased_uniform_gaussian": lambda: pin_unbiased(oracle.UNIFORM, oracle.GAUSSIAN),
+    "unbiased_stratified_bernoulli": lambda: pin_unbiased(oracle.STRATIFIED, oracle.BERNOULLI_ODDS),
+    "unbiased_semi_poisson": lambda: pin_unbiased(oracle.SEMI_STRATIFIED, oracle.POISSON),
+    "unbiased_semi_bernoulli": lambda: pin_unbiased(oracle.SEMI_STRATIFIED, oracle.BERNOULLI_ODDS),
+    "semi_zero_half_poisson": pin_semi_zero_half_poisson,
+    "adam_closed_forms": pin_adam_closed_forms,
+    "fd_gaussian": lambda: pin_finite_differences(oracle.GAUSSIAN),
+    "fd_bernoulli_stratified": lambda: pin_finite_differences(oracle.BERNOULLI_ODDS),
+    "fd_poisson_semi": lambda: pin_finite_differences(oracle.POISSON),
+}
