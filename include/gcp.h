@@ -1,0 +1,252 @@
+/*
+ * gcp.h -- C ABI of libgcp: the sampled gradient of generalized CP (GCP)
+ * tensor decomposition on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Kolda & Hong, "Stochastic Gradients for Large-Scale Tensor
+ * Decomposition".  One stochastic gradient draws sample indices (uniform,
+ * stratified with rejection, or semi-stratified; Sec. 4.1-4.3, Alg. 1-3),
+ * evaluates the CP model at them (eq. Mdef), applies the weighted loss
+ * derivative (eq. Y with the per-stratum weights of Sec. 4.1-4.3) and
+ * accumulates every mode's gradient as a sparse MTTKRP, G_k = Ytilde_(k) Z_k
+ * (eqs. mttkrp, Gks).  The Adam step with projection follows (Alg. 4).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Indices are 0-based (the paper counts from 1).  A multi-index i =
+ *   (i_1..i_d) has the row-major linear key L = ((i_1 n_2 + i_2) n_3 + ...).
+ * - Factor matrix A_k is n_k x r, row-major (a row is r contiguous values).
+ * - Dense X is row-major (last mode fastest).  COO X is nnz x d uint32 mode
+ *   indices, row-major, plus nnz values; no coordinate may appear twice.
+ * - Every pointer argument except the descriptor structs themselves is DEVICE
+ *   memory owned by the caller.  The library never allocates; each call that
+ *   needs scratch space takes a caller-owned workspace whose size is given by
+ *   the matching *_workspace_bytes() query.
+ * - Every call is asynchronous on the caller's stream and validates its
+ *   arguments on the host only (no device synchronisation).  On failure it
+ *   returns a non-zero gcp_status, launches nothing, and gcp_last_error()
+ *   returns a message for the calling thread.
+ * - Random draws: Philox4x64-10 (Salmon et al., SC'11) with key =
+ *   (seed, problem_id) and counter = (j, iteration, purpose, block); word k of
+ *   sample j's stream is word k mod 4 of block k / 4, and randi(n) =
+ *   floor(w * n / 2^64).  Purposes: 0 uniform draws and semi-stratified
+ *   "zeros", 1 nonzero picks, 2 rejection candidates.  The same (seed,
+ *   problem_id, iteration) always yields the same samples.
+ * - Sample order: for stratified and semi-stratified sampling the p nonzero
+ *   samples come first (j = 0..p-1), then the q zero samples.  Stratified
+ *   zeros are the first q accepted rejection candidates in counter order.
+ */
+#ifndef GCP_H
+#define GCP_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GCP_ABI_VERSION 1
+#define GCP_MAX_D 8        /* modes per tensor */
+#define GCP_MAX_RANK 64    /* CP rank r */
+
+typedef enum gcp_status {
+    GCP_OK = 0,
+    GCP_ERR_INVALID_ARG = 1,   /* a null pointer, bad size, or inconsistent argument */
+    GCP_ERR_UNSUPPORTED = 2,   /* valid by the method but outside what this build handles */
+    GCP_ERR_HIP = 3,           /* a HIP runtime call failed (launch error) */
+    GCP_ERR_WORKSPACE = 4      /* workspace smaller than the *_workspace_bytes() query */
+} gcp_status;
+
+typedef enum gcp_dtype { GCP_F32 = 0, GCP_F64 = 1, GCP_BF16 = 2 } gcp_dtype;
+
+/* Losses f(x, m) and g = df/dm (paper, Sec. 1 and 4.2).  eps is added where
+ * the paper writes log m or x/m:
+ *   GAUSSIAN        f = (x - m)^2,                  g = 2 (m - x)
+ *   BERNOULLI_ODDS  f = log(m + 1) - x log(m + eps), g = 1/(m + 1) - x/(m + eps)
+ *   POISSON         f = m - x log(m + eps),          g = 1 - x/(m + eps)        */
+typedef enum gcp_loss {
+    GCP_LOSS_GAUSSIAN = 0,
+    GCP_LOSS_BERNOULLI_ODDS = 1,
+    GCP_LOSS_POISSON = 2
+} gcp_loss;
+
+/* Samplers: UNIFORM (Sec. 4.1, Alg. 1; s draws with replacement, weight
+ * omega/s); STRATIFIED (Sec. 4.2, Alg. 2; p nonzeros with weight eta/p, q zeros
+ * by rejection with weight zeta/q); SEMI_STRATIFIED (Sec. 4.3, Alg. 3; p
+ * nonzeros with weight eta/p and derivative g(x,m) - g(0,m), q uniform
+ * "zeros" with x := 0 and weight omega/q).  omega = prod n_k, eta = nnz,
+ * zeta = omega - eta. */
+typedef enum gcp_sampler {
+    GCP_SAMPLER_UNIFORM = 0,
+    GCP_SAMPLER_STRATIFIED = 1,
+    GCP_SAMPLER_SEMI_STRATIFIED = 2
+} gcp_sampler;
+
+/* Per-sample stratum codes written by gcp_sample and read by gcp_loss_grad.
+ * ytilde = w * g(x, m) except NZ_CORR, where ytilde = w * (g(x,m) - g(0,m)). */
+typedef enum gcp_stratum {
+    GCP_STRATUM_UNIFORM = 0,    /* w = omega / s  */
+    GCP_STRATUM_NZ = 1,         /* w = eta / p    */
+    GCP_STRATUM_ZERO = 2,       /* w = zeta / q, x = 0 */
+    GCP_STRATUM_NZ_CORR = 3,    /* w = eta / p    */
+    GCP_STRATUM_SEMI_ZERO = 4   /* w = omega / q, x := 0 */
+} gcp_stratum;
+
+typedef enum gcp_format { GCP_DENSE = 0, GCP_COO = 1 } gcp_format;
+
+/* Alg. 4 writes A <- A - alpha Bhat / sqrt(Chat + eps) (INSIDE, the default);
+ * OUTSIDE is the Kingma-Ba form A <- A - alpha Bhat / (sqrt(Chat) + eps). */
+typedef enum gcp_eps_mode { GCP_EPS_INSIDE_SQRT = 0, GCP_EPS_OUTSIDE_SQRT = 1 } gcp_eps_mode;
+
+/* The data tensor X (Sec. 3.1: dense storage n^d, coordinate storage (d+1) nnz). */
+typedef struct gcp_tensor {
+    int32_t d;                   /* number of modes, 1..GCP_MAX_D */
+    int32_t format;              /* gcp_format */
+    int32_t vdtype;              /* value type: GCP_F32 or GCP_F64 */
+    int32_t reserved;            /* set to 0 */
+    int64_t dims[GCP_MAX_D];     /* n_1..n_d, each in [1, 2^32 - 1]; prod < 2^63 */
+    const void *values;          /* dense: prod(dims) values; COO: nnz values */
+    const uint32_t *coo_idx;     /* COO: nnz x d indices; NULL for dense */
+    int64_t nnz;                 /* COO: stored nonzeros (eta), < 2^32; dense: 0 */
+    const void *nz_table;        /* COO: table from gcp_nz_index_build (needed by
+                                    STRATIFIED and by UNIFORM on COO); else NULL */
+    int64_t nz_slots;            /* slots of nz_table */
+} gcp_tensor;
+
+/* The factor matrices A_1..A_d of the CP model (eq. Mdef). */
+typedef struct gcp_factors {
+    int32_t dtype;               /* storage: GCP_F32, GCP_F64 or GCP_BF16 */
+    int32_t reserved;            /* set to 0 */
+    int64_t rank;                /* r, 1..GCP_MAX_RANK */
+    const void *A[GCP_MAX_D];    /* A[k]: dims[k] x rank, row-major, device */
+} gcp_factors;
+
+/* What one stochastic gradient samples. */
+typedef struct gcp_sampling {
+    int32_t sampler;             /* gcp_sampler */
+    int32_t reserved;            /* set to 0 */
+    int64_t s;                   /* UNIFORM: number of samples (> 0) */
+    int64_t p;                   /* STRATIFIED / SEMI: nonzero samples (>= 0) */
+    int64_t q;                   /* STRATIFIED / SEMI: zero samples (>= 0) */
+    uint64_t seed;               /* Philox key word 0 */
+    uint64_t problem_id;         /* Philox key word 1 */
+    uint64_t iteration;          /* Philox counter word 1: one value per gradient */
+    double rho;                  /* STRATIFIED: rejection candidates are drawn in a
+                                    first batch of ceil(rho * q * omega / zeta);
+                                    rho <= 0 selects 1.1 (Sec. 4.2, App. B).  The
+                                    samples never depend on rho. */
+} gcp_sampling;
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *gcp_last_error(void);
+int gcp_abi_version(void);
+
+/* ---------------------------------------------------------------------------
+ * Nonzero index (Sec. 4.2: rejection needs a membership test of the sampled
+ * index against the list of nonzeros; the paper suggests hash tables).
+ * An open-addressing table of the nonzeros' linear keys and their COO
+ * positions: 8-byte keys then 4-byte positions, 12 bytes per slot.
+ * gcp_nz_table_slots(nnz) returns the power of two >= 2 nnz (at least 64) to
+ * use.  gcp_nz_index_build clears and fills `table` (gcp_nz_table_bytes(slots)
+ * bytes of device memory) from X's coordinates; X->nz_table is not read.
+ * Rebuild whenever X's coordinates change. */
+int64_t gcp_nz_table_slots(int64_t nnz);
+size_t gcp_nz_table_bytes(int64_t slots);
+gcp_status gcp_nz_index_build(const gcp_tensor *X, void *table, int64_t slots,
+                              hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * gcp_sample -- the sampling lines of Alg. 1 (uniform), Alg. 2 (nonzero picks
+ * xi = randi(eta) and the rejection loop for zeros) and Alg. 3 (nonzero picks
+ * and "zeros" drawn without rejection).
+ * Writes S = s (UNIFORM) or p + q samples:
+ *   idx[S * d]   uint32 mode indices of each sample
+ *   xval[S]      X at the sample (X->vdtype); 0 for the zero strata
+ *   stratum[S]   gcp_stratum code of each sample
+ * STRATIFIED needs q = 0 or zeta > 0, and X->nz_table.  UNIFORM on a COO
+ * tensor looks values up through X->nz_table.  ws: gcp_sample_workspace_bytes
+ * bytes (0 except for STRATIFIED).  The rejection loop is exact: if the first
+ * candidate batch holds fewer than q zeros, a device-side loop continues the
+ * counter stream until q are found (no host round trip). */
+size_t gcp_sample_workspace_bytes(const gcp_tensor *X, const gcp_sampling *cfg);
+gcp_status gcp_sample(const gcp_tensor *X, const gcp_sampling *cfg,
+                      uint32_t *idx, void *xval, uint8_t *stratum,
+                      void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * gcp_loss_grad -- model entries and weighted derivatives at given samples
+ * (Alg. 1-3: m_i = sum_j prod_k A_k(i_k, j), then ytilde_i += w g(x_i, m_i)).
+ * Weights come from the stratum codes, X's dims and nnz, and cfg's s, p, q.
+ *   ytilde[S]   out; F64 when M->dtype is GCP_F64, else F32 (computed in F32)
+ *   loss_sum    nullable device double; the call ADDS the weighted loss
+ *               estimate sum_i w f(x_i, m_i) (eqs. Fhat, Fhat-strat; for the
+ *               NZ_CORR stratum w (f(x,m) - f(0,m))).
+ * Duplicate samples are independent entries (their contributions add). */
+gcp_status gcp_loss_grad(gcp_loss loss, const gcp_tensor *X, const gcp_sampling *cfg,
+                         const gcp_factors *M, const uint32_t *idx, const void *xval,
+                         const uint8_t *stratum, int64_t S, double eps,
+                         void *ytilde, double *loss_sum, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * gcp_mttkrp -- the sparse MTTKRP of every mode over S samples (eqs. mttkrp,
+ * Gks; Alg. 1-3 last loop): G_k(i_k, :) += ytilde_i * prod_{k' != k} A_k'(i_k', :).
+ *   G[k]        out, dims[k] x rank row-major; F64 when M->dtype is GCP_F64,
+ *               else F32.  Overwritten unless `accumulate` is non-zero.
+ * Sums are accumulated in FP64 in the workspace
+ * (gcp_mttkrp_workspace_bytes bytes) and rounded once into G. */
+size_t gcp_mttkrp_workspace_bytes(const gcp_tensor *X, const gcp_factors *M);
+gcp_status gcp_mttkrp(const gcp_tensor *X, const gcp_factors *M, const uint32_t *idx,
+                      const void *ytilde, int64_t S, void *const *G, int accumulate,
+                      void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * gcp_sampled_grad -- the whole stochastic gradient of Alg. 1 / 2 / 3 in as
+ * few launches as possible: draws, model entries, derivatives and the MTTKRP
+ * of every mode, without writing the samples out.  Same samples as
+ * gcp_sample with the same cfg; G equal to gcp_sample -> gcp_loss_grad ->
+ * gcp_mttkrp up to floating-point summation order.  G and loss_sum as in
+ * gcp_mttkrp and gcp_loss_grad (G is overwritten). */
+size_t gcp_sampled_grad_workspace_bytes(const gcp_tensor *X, const gcp_factors *M,
+                                        const gcp_sampling *cfg);
+gcp_status gcp_sampled_grad(gcp_loss loss, const gcp_tensor *X, const gcp_factors *M,
+                            const gcp_sampling *cfg, double eps, void *const *G,
+                            double *loss_sum, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * gcp_adam_step -- one Adam step with projection over P parameters at once
+ * (Alg. 4: B <- b1 B + (1-b1) G; C <- b2 C + (1-b2) G^2; Bhat = B/(1-b1^t);
+ * Chat = C/(1-b2^t); A <- max(A - alpha Bhat / sqrt(Chat + eps), lower)).
+ * All modes' factors are updated together from gradients taken at the same
+ * A, so A, G, B, C are flat arrays covering sum_k n_k r parameters.
+ *   dtype GCP_F64: A, G, B, C double.  GCP_F32: float.  GCP_BF16: A is the
+ *   bf16 copy used for gathers, A_master the float master that is updated
+ *   (then rounded to nearest even into A); G, B, C float.
+ *   state[2]  device int64: state[0] is t, the number of steps taken so far;
+ *             state[1] is internal and must be 0 between calls.  Zero both
+ *             before the first step.  The step uses t + 1 (so the first step
+ *             divides by 1 - b^1) and leaves state[0] = t + 1, all on device.
+ *   lower     projection bound; -INFINITY for none.
+ * Calls on one state must not overlap. */
+gcp_status gcp_adam_step(int64_t P, gcp_dtype dtype, void *A, float *A_master,
+                         const void *G, void *B, void *C, int64_t *state,
+                         double alpha, double beta1, double beta2, double eps,
+                         double lower, gcp_eps_mode eps_mode, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Kernel timing for measurement harnesses (results never depend on it).
+ * gcp_timing_start(n) creates n pairs of HIP events up front (so timing adds
+ * no allocation to the calls it measures) and arms them: each following
+ * gcp_sampled_grad call records one pair on its stream immediately around
+ * its gradient kernel (model entries, derivatives and MTTKRP scatter), until
+ * n pairs are used.  gcp_timing_stop waits for the recorded events, writes
+ * the summed kernel time in milliseconds and the number of timed launches,
+ * and destroys the events.  Host-global: one timing session at a time. */
+gcp_status gcp_timing_start(int64_t max_launches);
+gcp_status gcp_timing_stop(double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GCP_H */

@@ -1,0 +1,291 @@
+"""Torch-facing binding of libgcp: argument marshalling only.
+
+Every step of the sampled GCP gradient runs in the HIP kernels behind the C
+ABI (include/gcp.h).  torch supplies device memory (tensors, workspaces) and
+the current HIP stream; nothing here computes any part of the method.
+
+Index tensors hold the ABI's uint32 mode indices in torch.int32 storage.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import (BF16, COO, DENSE, F32, F64, GcpFactors, GcpSampling, GcpTensor, check, lib)
+
+LOSSES = {"gaussian": _lib.GAUSSIAN, "bernoulli_odds": _lib.BERNOULLI_ODDS, "poisson": _lib.POISSON}
+SAMPLERS = {"uniform": _lib.UNIFORM, "stratified": _lib.STRATIFIED, "semi_stratified": _lib.SEMI_STRATIFIED}
+LOSS_EPS = 1e-10
+
+_TORCH_DTYPE = {F32: torch.float32, F64: torch.float64, BF16: torch.bfloat16}
+_CODE = {torch.float32: F32, torch.float64: F64, torch.bfloat16: BF16}
+
+
+def _stream(stream: Optional[torch.cuda.Stream] = None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else int(t.data_ptr())
+
+
+def _loss_code(loss) -> int:
+    return LOSSES[loss] if isinstance(loss, str) else int(loss)
+
+
+def _sampler_code(sampler) -> int:
+    return SAMPLERS[sampler] if isinstance(sampler, str) else int(sampler)
+
+
+# ---------------------------------------------------------------------------
+# data tensor
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class DataTensor:
+    """Device description of X: dense row-major values or COO (indices + values)."""
+    dims: tuple
+    values: torch.Tensor
+    coo_idx: Optional[torch.Tensor] = None      # [nnz, d] int32 (uint32 bits)
+    nz_table: Optional[torch.Tensor] = None     # uint8 bytes of the nonzero hash
+    nz_slots: int = 0
+
+    @property
+    def d(self) -> int:
+        return len(self.dims)
+
+    @property
+    def nnz(self) -> int:
+        return 0 if self.coo_idx is None else int(self.coo_idx.shape[0])
+
+    @property
+    def is_dense(self) -> bool:
+        return self.coo_idx is None
+
+    @property
+    def omega(self) -> int:
+        return math.prod(int(n) for n in self.dims)
+
+    def struct(self) -> GcpTensor:
+        t = GcpTensor()
+        t.d = self.d
+        t.format = DENSE if self.is_dense else COO
+        t.vdtype = _CODE[self.values.dtype]
+        for k, n in enumerate(self.dims):
+            t.dims[k] = int(n)
+        t.values = _ptr(self.values)
+        t.coo_idx = _ptr(self.coo_idx)
+        t.nnz = self.nnz
+        t.nz_table = _ptr(self.nz_table)
+        t.nz_slots = int(self.nz_slots)
+        return t
+
+
+def dense_tensor(X: torch.Tensor) -> DataTensor:
+    if X.dtype not in (torch.float32, torch.float64) or not X.is_contiguous():
+        raise ValueError("dense X must be a contiguous float32/float64 tensor")
+    return DataTensor(tuple(X.shape), X)
+
+
+def coo_tensor(dims: Sequence[int], coo_idx: torch.Tensor, values: torch.Tensor,
+               build_index: bool = True, stream=None) -> DataTensor:
+    """COO tensor; builds the nonzero hash (gcp_nz_index_build) unless told not to."""
+    if coo_idx.dtype != torch.int32 or coo_idx.dim() != 2 or coo_idx.shape[1] != len(dims):
+        raise ValueError("coo_idx must be an [nnz, d] int32 tensor")
+    X = DataTensor(tuple(int(n) for n in dims), values.contiguous(), coo_idx.contiguous())
+    if build_index:
+        L = lib()
+        slots = int(L.gcp_nz_table_slots(X.nnz))
+        table = torch.empty(int(L.gcp_nz_table_bytes(slots)), dtype=torch.uint8, device=values.device)
+        t = X.struct()
+        check(L.gcp_nz_index_build(ctypes.byref(t), _ptr(table), slots, _stream(stream)))
+        X.nz_table, X.nz_slots = table, slots
+    return X
+
+
+# ---------------------------------------------------------------------------
+# factors and sampling configuration
+# ---------------------------------------------------------------------------
+
+class Factors:
+    """A_1..A_d in one flat buffer (row-major n_k x r blocks), as the Adam step wants.
+
+    dtype float64/float32: ``flat`` is the parameter vector.  bfloat16: ``master``
+    (float32) is updated by Adam and ``flat`` is its bf16 copy used for gathers.
+    """
+
+    def __init__(self, dims: Sequence[int], rank: int, dtype: torch.dtype, device, init=None):
+        self.dims = tuple(int(n) for n in dims)
+        self.rank = int(rank)
+        self.dtype = dtype
+        self.sizes = [n * self.rank for n in self.dims]
+        self.P = sum(self.sizes)
+        self.flat = torch.zeros(self.P, dtype=dtype, device=device)
+        self.master = torch.zeros(self.P, dtype=torch.float32, device=device) if dtype == torch.bfloat16 else None
+        if init is not None:
+            self.load(init)
+
+    def _views(self, buf: torch.Tensor) -> List[torch.Tensor]:
+        out, off = [], 0
+        for n, sz in zip(self.dims, self.sizes):
+            out.append(buf[off:off + sz].view(n, self.rank))
+            off += sz
+        return out
+
+    @property
+    def A(self) -> List[torch.Tensor]:
+        return self._views(self.flat)
+
+    def load(self, mats) -> None:
+        src = torch.cat([torch.as_tensor(m).reshape(-1).to(torch.float64) for m in mats])
+        if self.master is not None:
+            self.master.copy_(src.to(torch.float32))
+            self.flat.copy_(self.master.to(torch.bfloat16))
+        else:
+            self.flat.copy_(src.to(self.dtype))
+
+    def grad_buffer(self) -> torch.Tensor:
+        gdt = torch.float64 if self.dtype == torch.float64 else torch.float32
+        return torch.zeros(self.P, dtype=gdt, device=self.flat.device)
+
+    def grad_views(self, buf: torch.Tensor) -> List[torch.Tensor]:
+        return self._views(buf)
+
+    def struct(self) -> GcpFactors:
+        m = GcpFactors()
+        m.dtype = _CODE[self.dtype]
+        m.rank = self.rank
+        for k, a in enumerate(self.A):
+            m.A[k] = _ptr(a)
+        return m
+
+
+def sampling(sampler="uniform", s=0, p=0, q=0, seed=0, problem_id=0, iteration=0, rho=0.0) -> GcpSampling:
+    c = GcpSampling()
+    c.sampler = _sampler_code(sampler)
+    c.s, c.p, c.q = int(s), int(p), int(q)
+    c.seed, c.problem_id, c.iteration = int(seed), int(problem_id), int(iteration)
+    c.rho = float(rho)
+    return c
+
+
+def n_samples(cfg: GcpSampling) -> int:
+    return cfg.s if cfg.sampler == _lib.UNIFORM else cfg.p + cfg.q
+
+
+def _ptr_array(tensors) -> ctypes.Array:
+    return (ctypes.c_void_p * len(tensors))(*[_ptr(t) for t in tensors])
+
+
+# ---------------------------------------------------------------------------
+# entry points
+# ---------------------------------------------------------------------------
+
+def sample(X: DataTensor, cfg: GcpSampling, stream=None):
+    """gcp_sample: (idx [S, d] int32, xval [S], stratum [S] uint8)."""
+    L = lib()
+    dev = X.values.device
+    S = n_samples(cfg)
+    idx = torch.empty((max(S, 1), X.d), dtype=torch.int32, device=dev)
+    xval = torch.empty(max(S, 1), dtype=X.values.dtype, device=dev)
+    st = torch.empty(max(S, 1), dtype=torch.uint8, device=dev)
+    t = X.struct()
+    nbytes = int(L.gcp_sample_workspace_bytes(ctypes.byref(t), ctypes.byref(cfg)))
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    check(L.gcp_sample(ctypes.byref(t), ctypes.byref(cfg), _ptr(idx), _ptr(xval), _ptr(st),
+                       _ptr(ws), nbytes, _stream(stream)))
+    return idx[:S], xval[:S], st[:S]
+
+
+def loss_grad(loss, X: DataTensor, cfg: GcpSampling, M: Factors, idx, xval, stratum,
+              eps: float = LOSS_EPS, with_loss: bool = False, stream=None):
+    """gcp_loss_grad: ytilde [S] (and the loss estimate as a device double)."""
+    L = lib()
+    S = int(idx.shape[0])
+    ydt = torch.float64 if M.dtype == torch.float64 else torch.float32
+    y = torch.empty(max(S, 1), dtype=ydt, device=X.values.device)
+    fs = torch.zeros(1, dtype=torch.float64, device=X.values.device) if with_loss else None
+    t, m = X.struct(), M.struct()
+    check(L.gcp_loss_grad(_loss_code(loss), ctypes.byref(t), ctypes.byref(cfg), ctypes.byref(m),
+                          _ptr(idx), _ptr(xval), _ptr(stratum), S, float(eps), _ptr(y), _ptr(fs),
+                          _stream(stream)))
+    return (y[:S], fs) if with_loss else y[:S]
+
+
+def mttkrp(X: DataTensor, M: Factors, idx, ytilde, out: Optional[List[torch.Tensor]] = None,
+           accumulate: bool = False, stream=None) -> List[torch.Tensor]:
+    """gcp_mttkrp: G_k for every mode (list of n_k x r tensors)."""
+    L = lib()
+    if out is None:
+        out = M.grad_views(M.grad_buffer())
+    t, m = X.struct(), M.struct()
+    nbytes = int(L.gcp_mttkrp_workspace_bytes(ctypes.byref(t), ctypes.byref(m)))
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=X.values.device)
+    check(L.gcp_mttkrp(ctypes.byref(t), ctypes.byref(m), _ptr(idx), _ptr(ytilde), int(idx.shape[0]),
+                       _ptr_array(out), int(bool(accumulate)), _ptr(ws), nbytes, _stream(stream)))
+    return out
+
+
+class SampledGrad:
+    """Reusable gcp_sampled_grad call: descriptors and workspace set up once."""
+
+    def __init__(self, loss, X: DataTensor, M: Factors, cfg: GcpSampling, eps: float = LOSS_EPS,
+                 out: Optional[List[torch.Tensor]] = None, with_loss: bool = False):
+        L = lib()
+        self.loss = _loss_code(loss)
+        self.X, self.M, self.cfg, self.eps = X, M, cfg, float(eps)
+        self.t, self.m = X.struct(), M.struct()
+        self.gbuf = None
+        if out is None:
+            self.gbuf = M.grad_buffer()
+            out = M.grad_views(self.gbuf)
+        self.out = out
+        self.out_ptrs = _ptr_array(out)
+        self.nbytes = int(L.gcp_sampled_grad_workspace_bytes(ctypes.byref(self.t), ctypes.byref(self.m),
+                                                              ctypes.byref(cfg)))
+        self.ws = torch.empty(max(self.nbytes, 1), dtype=torch.uint8, device=X.values.device)
+        self.loss_sum = torch.zeros(1, dtype=torch.float64, device=X.values.device) if with_loss else None
+
+    def __call__(self, iteration: Optional[int] = None, stream=None) -> List[torch.Tensor]:
+        if iteration is not None:
+            self.cfg.iteration = int(iteration)
+        check(lib().gcp_sampled_grad(self.loss, ctypes.byref(self.t), ctypes.byref(self.m),
+                                     ctypes.byref(self.cfg), self.eps, self.out_ptrs, _ptr(self.loss_sum),
+                                     _ptr(self.ws), self.nbytes, _stream(stream)))
+        return self.out
+
+
+def sampled_grad(loss, X: DataTensor, M: Factors, cfg: GcpSampling, eps: float = LOSS_EPS,
+                 out=None, with_loss: bool = False, stream=None):
+    """gcp_sampled_grad in one call: G_k (and the loss estimate if asked)."""
+    call = SampledGrad(loss, X, M, cfg, eps, out, with_loss)
+    G = call(stream=stream)
+    return (G, call.loss_sum) if with_loss else G
+
+
+class Adam:
+    """Adam moments B, C and the device step counter for a Factors set (Alg. 4)."""
+
+    def __init__(self, M: Factors, lr: float = 0.01, beta1: float = 0.9, beta2: float = 0.999,
+                 eps: float = 1e-8, lower: float = -math.inf, eps_mode: int = _lib.EPS_INSIDE_SQRT):
+        self.M = M
+        mdt = torch.float64 if M.dtype == torch.float64 else torch.float32
+        dev = M.flat.device
+        self.B = torch.zeros(M.P, dtype=mdt, device=dev)
+        self.C = torch.zeros(M.P, dtype=mdt, device=dev)
+        self.state = torch.zeros(2, dtype=torch.int64, device=dev)
+        self.lr, self.beta1, self.beta2, self.eps, self.lower = lr, beta1, beta2, eps, lower
+        self.eps_mode = eps_mode
+
+    def step(self, G_flat: torch.Tensor, stream=None) -> None:
+        M = self.M
+        check(lib().gcp_adam_step(M.P, _CODE[M.dtype], _ptr(M.flat), _ptr(M.master), _ptr(G_flat),
+                                  _ptr(self.B), _ptr(self.C), _ptr(self.state), float(self.lr),
+                                  float(self.beta1), float(self.beta2), float(self.eps), float(self.lower),
+                                  int(self.eps_mode), _stream(stream)))

@@ -1,0 +1,403 @@
+// abi.cpp -- the extern "C" entry points of libgcp: host-side argument
+// validation, workspace sizing and carving, and the launch sequence of each
+// call.  No device synchronisation and no allocation happen here.
+#include <hip/hip_runtime_api.h>
+
+#include <math.h>
+#include <stdio.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "gcp.h"
+
+namespace gcp {
+
+static thread_local std::string g_last_error;
+
+gcp_status set_error(gcp_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+gcp_status check_launch(const char* what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(GCP_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    return GCP_OK;
+}
+
+static unsigned __int128 omega128(const gcp_tensor* X) {
+    unsigned __int128 w = 1;
+    for (int k = 0; k < X->d; ++k) w *= (unsigned __int128)(uint64_t)X->dims[k];
+    return w;
+}
+
+static double omega_d(const gcp_tensor* X) {
+    double w = 1.0;
+    for (int k = 0; k < X->d; ++k) w *= (double)X->dims[k];
+    return w;
+}
+
+void stratum_weights(const gcp_tensor* X, const gcp_sampling* cfg, double w[5]) {
+    const double omega = omega_d(X);
+    const double eta = (double)X->nnz;
+    w[GCP_STRATUM_UNIFORM] = cfg->s > 0 ? omega / (double)cfg->s : 0.0;
+    w[GCP_STRATUM_NZ] = cfg->p > 0 ? eta / (double)cfg->p : 0.0;
+    w[GCP_STRATUM_ZERO] = cfg->q > 0 ? (omega - eta) / (double)cfg->q : 0.0;
+    w[GCP_STRATUM_NZ_CORR] = w[GCP_STRATUM_NZ];
+    w[GCP_STRATUM_SEMI_ZERO] = cfg->q > 0 ? omega / (double)cfg->q : 0.0;
+}
+
+int64_t rejection_batch(const gcp_tensor* X, const gcp_sampling* cfg) {
+    const double omega = omega_d(X);
+    const double zeta = omega - (double)X->nnz;
+    const double rho = cfg->rho > 0.0 ? cfg->rho : 1.1;
+    double n = ceil(rho * (double)cfg->q * omega / zeta);
+    if (!(n >= 1.0)) n = 1.0;
+    if (n > 4.0e15) n = 4.0e15;
+    return (int64_t)n;
+}
+
+RejScratch carve_rejection(Carver& c, void* base, int64_t ncand) {
+    RejScratch r{};
+    r.nblk = (ncand + kRejTile - 1) / kRejTile;
+    if (r.nblk < 1) r.nblk = 1;
+    r.block_count = c.take<uint32_t>(base, (size_t)r.nblk);
+    r.block_offset = c.take<uint64_t>(base, (size_t)r.nblk);
+    r.total = c.take<uint64_t>(base, 1);
+    r.status = c.take<uint32_t>(base, 1);
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------
+static gcp_status check_tensor(const gcp_tensor* X) {
+    if (!X) return set_error(GCP_ERR_INVALID_ARG, "X is NULL");
+    if (X->d < 1 || X->d > GCP_MAX_D) return set_error(GCP_ERR_INVALID_ARG, "X->d must be in [1, 8]");
+    if (X->format != GCP_DENSE && X->format != GCP_COO)
+        return set_error(GCP_ERR_INVALID_ARG, "X->format must be GCP_DENSE or GCP_COO");
+    if (X->vdtype != GCP_F32 && X->vdtype != GCP_F64)
+        return set_error(GCP_ERR_INVALID_ARG, "X->vdtype must be GCP_F32 or GCP_F64");
+    for (int k = 0; k < X->d; ++k)
+        if (X->dims[k] < 1 || X->dims[k] > (int64_t)0xFFFFFFFFll)
+            return set_error(GCP_ERR_INVALID_ARG, "X->dims[" + std::to_string(k) + "] must be in [1, 2^32 - 1]");
+    if (omega128(X) >= ((unsigned __int128)1 << 63))
+        return set_error(GCP_ERR_UNSUPPORTED, "the number of tensor entries must be below 2^63");
+    if (X->format == GCP_DENSE) {
+        if (!X->values) return set_error(GCP_ERR_INVALID_ARG, "dense X->values is NULL");
+    } else {
+        if (X->nnz < 0 || X->nnz > (int64_t)0xFFFFFFFFll)
+            return set_error(GCP_ERR_INVALID_ARG, "X->nnz must be in [0, 2^32 - 1]");
+        if ((unsigned __int128)(uint64_t)X->nnz > omega128(X))
+            return set_error(GCP_ERR_INVALID_ARG, "X->nnz exceeds the number of entries");
+        if (X->nnz > 0 && (!X->coo_idx || !X->values))
+            return set_error(GCP_ERR_INVALID_ARG, "COO X needs coo_idx and values");
+    }
+    return GCP_OK;
+}
+
+static gcp_status check_table(const gcp_tensor* X) {
+    if (!X->nz_table) return set_error(GCP_ERR_INVALID_ARG, "X->nz_table is NULL (build it with gcp_nz_index_build)");
+    if (X->nz_slots < 2 || (X->nz_slots & (X->nz_slots - 1)) || X->nz_slots <= X->nnz)
+        return set_error(GCP_ERR_INVALID_ARG, "X->nz_slots must be a power of two above nnz");
+    return GCP_OK;
+}
+
+static gcp_status check_sampling(const gcp_tensor* X, const gcp_sampling* cfg) {
+    if (!cfg) return set_error(GCP_ERR_INVALID_ARG, "cfg is NULL");
+    switch (cfg->sampler) {
+    case GCP_SAMPLER_UNIFORM:
+        if (cfg->s < 0) return set_error(GCP_ERR_INVALID_ARG, "cfg->s must be >= 0");
+        if (X->format == GCP_COO && cfg->s > 0) {
+            if (gcp_status st = check_table(X)) return st;
+        }
+        break;
+    case GCP_SAMPLER_STRATIFIED:
+    case GCP_SAMPLER_SEMI_STRATIFIED: {
+        if (X->format != GCP_COO)
+            return set_error(GCP_ERR_INVALID_ARG, "stratified and semi-stratified sampling need a COO tensor");
+        if (cfg->p < 0 || cfg->q < 0) return set_error(GCP_ERR_INVALID_ARG, "cfg->p and cfg->q must be >= 0");
+        if (cfg->p > 0 && X->nnz == 0) return set_error(GCP_ERR_INVALID_ARG, "p > 0 needs at least one nonzero");
+        if (cfg->sampler == GCP_SAMPLER_STRATIFIED && cfg->q > 0) {
+            if (gcp_status st = check_table(X)) return st;
+            const double omega = omega_d(X), zeta = omega - (double)X->nnz;
+            if (!(zeta > 0.0)) return set_error(GCP_ERR_INVALID_ARG, "stratified zeros requested but X has no zeros");
+            if (zeta < omega * (1.0 / 1048576.0))
+                return set_error(GCP_ERR_UNSUPPORTED, "rejection needs zeros to be at least 2^-20 of the entries");
+        }
+        break;
+    }
+    default:
+        return set_error(GCP_ERR_INVALID_ARG, "cfg->sampler is not a gcp_sampler");
+    }
+    return GCP_OK;
+}
+
+static gcp_status check_factors(const gcp_tensor* X, const gcp_factors* M) {
+    if (!M) return set_error(GCP_ERR_INVALID_ARG, "M is NULL");
+    if (M->dtype != GCP_F32 && M->dtype != GCP_F64 && M->dtype != GCP_BF16)
+        return set_error(GCP_ERR_INVALID_ARG, "M->dtype must be GCP_F32, GCP_F64 or GCP_BF16");
+    if (M->rank < 1) return set_error(GCP_ERR_INVALID_ARG, "M->rank must be >= 1");
+    if (M->rank > GCP_MAX_RANK) return set_error(GCP_ERR_UNSUPPORTED, "M->rank above 64 is not supported");
+    for (int k = 0; k < X->d; ++k)
+        if (!M->A[k]) return set_error(GCP_ERR_INVALID_ARG, "M->A[" + std::to_string(k) + "] is NULL");
+    return GCP_OK;
+}
+
+static gcp_status check_loss(gcp_loss loss) {
+    if (loss != GCP_LOSS_GAUSSIAN && loss != GCP_LOSS_BERNOULLI_ODDS && loss != GCP_LOSS_POISSON)
+        return set_error(GCP_ERR_INVALID_ARG, "loss is not a gcp_loss");
+    return GCP_OK;
+}
+
+static int64_t sample_count(const gcp_sampling* cfg) {
+    return cfg->sampler == GCP_SAMPLER_UNIFORM ? cfg->s : cfg->p + cfg->q;
+}
+
+static size_t sample_ws(const gcp_tensor* X, const gcp_sampling* cfg, Carver& c, void* base, RejScratch* rs) {
+    if (cfg->sampler == GCP_SAMPLER_STRATIFIED && cfg->q > 0) {
+        RejScratch r = carve_rejection(c, base, rejection_batch(X, cfg));
+        if (rs) *rs = r;
+    }
+    return c.bytes();
+}
+
+// Kernel timing session (see gcp_timing_start in gcp.h).
+struct Timing {
+    std::mutex mu;
+    std::vector<hipEvent_t> start, stop;
+    size_t used = 0;
+    bool armed = false;
+};
+static Timing g_timing;
+
+static void timing_record(bool before, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    if (!g_timing.armed) return;
+    if (before) {
+        if (g_timing.used < g_timing.start.size()) (void)hipEventRecord(g_timing.start[g_timing.used], s);
+    } else if (g_timing.used < g_timing.stop.size()) {
+        (void)hipEventRecord(g_timing.stop[g_timing.used], s);
+        ++g_timing.used;
+    }
+}
+
+}  // namespace gcp
+
+using namespace gcp;
+
+extern "C" {
+
+const char* gcp_last_error(void) { return g_last_error.c_str(); }
+
+int gcp_abi_version(void) { return GCP_ABI_VERSION; }
+
+int64_t gcp_nz_table_slots(int64_t nnz) {
+    int64_t s = 64;
+    while (s < 2 * nnz) s <<= 1;
+    return s;
+}
+
+size_t gcp_nz_table_bytes(int64_t slots) { return slots > 0 ? (size_t)slots * 12u : 0u; }
+
+gcp_status gcp_nz_index_build(const gcp_tensor* X, void* table, int64_t slots, hipStream_t stream) {
+    clear_error();
+    if (gcp_status st = check_tensor(X)) return st;
+    if (X->format != GCP_COO) return set_error(GCP_ERR_INVALID_ARG, "gcp_nz_index_build needs a COO tensor");
+    if (!table) return set_error(GCP_ERR_INVALID_ARG, "table is NULL");
+    if (slots < 2 || (slots & (slots - 1)) || slots <= X->nnz)
+        return set_error(GCP_ERR_INVALID_ARG, "slots must be a power of two above nnz");
+    return launch_nz_build(X, table, slots, stream);
+}
+
+size_t gcp_sample_workspace_bytes(const gcp_tensor* X, const gcp_sampling* cfg) {
+    if (!X || !cfg) return 0;
+    Carver c;
+    return sample_ws(X, cfg, c, nullptr, nullptr);
+}
+
+gcp_status gcp_sample(const gcp_tensor* X, const gcp_sampling* cfg, uint32_t* idx, void* xval, uint8_t* stratum,
+                      void* ws, size_t ws_bytes, hipStream_t stream) {
+    clear_error();
+    if (gcp_status st = check_tensor(X)) return st;
+    if (gcp_status st = check_sampling(X, cfg)) return st;
+    const int64_t S = sample_count(cfg);
+    if (S == 0) return GCP_OK;
+    if (!idx || !xval || !stratum) return set_error(GCP_ERR_INVALID_ARG, "idx, xval and stratum must be non-NULL");
+    Carver c;
+    RejScratch rs{};
+    const size_t need = sample_ws(X, cfg, c, ws, &rs);
+    if (need > 0 && (!ws || ws_bytes < need))
+        return set_error(GCP_ERR_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
+    if (cfg->sampler == GCP_SAMPLER_UNIFORM)
+        return launch_sample_direct(X, cfg, kKindUniform, cfg->s, 0, idx, xval, stratum, stream);
+    if (gcp_status st = launch_sample_direct(X, cfg, kKindNonzero, cfg->p, 0, idx, xval, stratum, stream)) return st;
+    if (cfg->sampler == GCP_SAMPLER_SEMI_STRATIFIED)
+        return launch_sample_direct(X, cfg, kKindSemiZero, cfg->q, cfg->p, idx, xval, stratum, stream);
+    return launch_rejection(X, cfg, rejection_batch(X, cfg), rs, idx, cfg->p, xval, stratum, stream);
+}
+
+gcp_status gcp_loss_grad(gcp_loss loss, const gcp_tensor* X, const gcp_sampling* cfg, const gcp_factors* M,
+                         const uint32_t* idx, const void* xval, const uint8_t* stratum, int64_t S, double eps,
+                         void* ytilde, double* loss_sum, hipStream_t stream) {
+    clear_error();
+    if (gcp_status st = check_loss(loss)) return st;
+    if (gcp_status st = check_tensor(X)) return st;
+    if (!cfg) return set_error(GCP_ERR_INVALID_ARG, "cfg is NULL");
+    if (gcp_status st = check_factors(X, M)) return st;
+    if (S < 0) return set_error(GCP_ERR_INVALID_ARG, "S must be >= 0");
+    if (S == 0) return GCP_OK;
+    if (!idx || !xval || !stratum || !ytilde)
+        return set_error(GCP_ERR_INVALID_ARG, "idx, xval, stratum and ytilde must be non-NULL");
+    return launch_loss_grad(loss, X, cfg, M, idx, xval, stratum, S, eps, ytilde, loss_sum, stream);
+}
+
+size_t gcp_mttkrp_workspace_bytes(const gcp_tensor* X, const gcp_factors* M) {
+    if (!X || !M || X->d < 1 || X->d > GCP_MAX_D) return 0;
+    Carver c;
+    c.take<double>(nullptr, (size_t)acc_layout(X, M).offset[X->d]);
+    return c.bytes();
+}
+
+gcp_status gcp_mttkrp(const gcp_tensor* X, const gcp_factors* M, const uint32_t* idx, const void* ytilde, int64_t S,
+                      void* const* G, int accumulate, void* ws, size_t ws_bytes, hipStream_t stream) {
+    clear_error();
+    if (gcp_status st = check_tensor(X)) return st;
+    if (gcp_status st = check_factors(X, M)) return st;
+    if (S < 0) return set_error(GCP_ERR_INVALID_ARG, "S must be >= 0");
+    if (!G) return set_error(GCP_ERR_INVALID_ARG, "G is NULL");
+    for (int k = 0; k < X->d; ++k)
+        if (!G[k]) return set_error(GCP_ERR_INVALID_ARG, "G[" + std::to_string(k) + "] is NULL");
+    if (S > 0 && (!idx || !ytilde)) return set_error(GCP_ERR_INVALID_ARG, "idx and ytilde must be non-NULL");
+    const size_t need = gcp_mttkrp_workspace_bytes(X, M);
+    if (!ws || ws_bytes < need) return set_error(GCP_ERR_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
+    const AccLayout L = acc_layout(X, M);
+    Carver c;
+    double* acc = c.take<double>(ws, (size_t)L.offset[X->d]);
+    if (gcp_status st = launch_fill_zero(acc, L.offset[X->d], stream)) return st;
+    if (gcp_status st = launch_mttkrp_list(X, M, idx, ytilde, S, acc, L, stream)) return st;
+    return launch_finalize(X, M, acc, L, G, accumulate, stream);
+}
+
+static size_t fused_ws(const gcp_tensor* X, const gcp_factors* M, const gcp_sampling* cfg, void* base, double** acc,
+                       uint32_t** zlist, RejScratch* rs) {
+    Carver c;
+    double* a = c.take<double>(base, (size_t)acc_layout(X, M).offset[X->d]);
+    if (acc) *acc = a;
+    if (cfg->sampler == GCP_SAMPLER_STRATIFIED && cfg->q > 0) {
+        uint32_t* z = c.take<uint32_t>(base, (size_t)cfg->q * (size_t)X->d);
+        if (zlist) *zlist = z;
+        RejScratch r = carve_rejection(c, base, rejection_batch(X, cfg));
+        if (rs) *rs = r;
+    }
+    return c.bytes();
+}
+
+size_t gcp_sampled_grad_workspace_bytes(const gcp_tensor* X, const gcp_factors* M, const gcp_sampling* cfg) {
+    if (!X || !M || !cfg || X->d < 1 || X->d > GCP_MAX_D) return 0;
+    return fused_ws(X, M, cfg, nullptr, nullptr, nullptr, nullptr);
+}
+
+gcp_status gcp_sampled_grad(gcp_loss loss, const gcp_tensor* X, const gcp_factors* M, const gcp_sampling* cfg,
+                            double eps, void* const* G, double* loss_sum, void* ws, size_t ws_bytes,
+                            hipStream_t stream) {
+    clear_error();
+    if (gcp_status st = check_loss(loss)) return st;
+    if (gcp_status st = check_tensor(X)) return st;
+    if (gcp_status st = check_sampling(X, cfg)) return st;
+    if (gcp_status st = check_factors(X, M)) return st;
+    if (!G) return set_error(GCP_ERR_INVALID_ARG, "G is NULL");
+    for (int k = 0; k < X->d; ++k)
+        if (!G[k]) return set_error(GCP_ERR_INVALID_ARG, "G[" + std::to_string(k) + "] is NULL");
+    const size_t need = gcp_sampled_grad_workspace_bytes(X, M, cfg);
+    if (!ws || ws_bytes < need) return set_error(GCP_ERR_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
+    double* acc = nullptr;
+    uint32_t* zlist = nullptr;
+    RejScratch rs{};
+    fused_ws(X, M, cfg, ws, &acc, &zlist, &rs);
+    const AccLayout L = acc_layout(X, M);
+    if (gcp_status st = launch_fill_zero(acc, L.offset[X->d], stream)) return st;
+    if (zlist) {
+        if (gcp_status st = launch_rejection(X, cfg, rejection_batch(X, cfg), rs, zlist, 0, nullptr, nullptr, stream))
+            return st;
+    }
+    timing_record(true, stream);
+    const gcp_status st = launch_fused(loss, X, M, cfg, eps, zlist, acc, L, loss_sum, stream);
+    timing_record(false, stream);
+    if (st) return st;
+    return launch_finalize(X, M, acc, L, G, 0, stream);
+}
+
+gcp_status gcp_timing_start(int64_t max_launches) {
+    clear_error();
+    if (max_launches < 1 || max_launches > (1 << 20))
+        return set_error(GCP_ERR_INVALID_ARG, "max_launches must be in [1, 2^20]");
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    if (g_timing.armed) return set_error(GCP_ERR_INVALID_ARG, "a timing session is already running");
+    g_timing.start.assign((size_t)max_launches, nullptr);
+    g_timing.stop.assign((size_t)max_launches, nullptr);
+    for (int64_t e = 0; e < max_launches; ++e) {
+        if (hipEventCreate(&g_timing.start[e]) != hipSuccess || hipEventCreate(&g_timing.stop[e]) != hipSuccess) {
+            for (auto& ev : g_timing.start) if (ev) (void)hipEventDestroy(ev);
+            for (auto& ev : g_timing.stop) if (ev) (void)hipEventDestroy(ev);
+            g_timing.start.clear();
+            g_timing.stop.clear();
+            return set_error(GCP_ERR_HIP, "hipEventCreate failed");
+        }
+    }
+    g_timing.used = 0;
+    g_timing.armed = true;
+    return GCP_OK;
+}
+
+gcp_status gcp_timing_stop(double* total_ms, int64_t* launches) {
+    clear_error();
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    if (!g_timing.armed) return set_error(GCP_ERR_INVALID_ARG, "no timing session is running");
+    double sum = 0.0;
+    gcp_status st = GCP_OK;
+    for (size_t e = 0; e < g_timing.used; ++e) {
+        float ms = 0.f;
+        if (hipEventSynchronize(g_timing.stop[e]) != hipSuccess ||
+            hipEventElapsedTime(&ms, g_timing.start[e], g_timing.stop[e]) != hipSuccess) {
+            st = set_error(GCP_ERR_HIP, "reading timing events failed");
+            break;
+        }
+        sum += ms;
+    }
+    for (auto& ev : g_timing.start) (void)hipEventDestroy(ev);
+    for (auto& ev : g_timing.stop) (void)hipEventDestroy(ev);
+    if (total_ms) *total_ms = sum;
+    if (launches) *launches = (int64_t)g_timing.used;
+    g_timing.start.clear();
+    g_timing.stop.clear();
+    g_timing.used = 0;
+    g_timing.armed = false;
+    return st;
+}
+
+gcp_status gcp_adam_step(int64_t P, gcp_dtype dtype, void* A, float* A_master, const void* G, void* B, void* C,
+                         int64_t* state, double alpha, double beta1, double beta2, double eps, double lower,
+                         gcp_eps_mode eps_mode, hipStream_t stream) {
+    clear_error();
+    if (P < 0) return set_error(GCP_ERR_INVALID_ARG, "P must be >= 0");
+    if (dtype != GCP_F32 && dtype != GCP_F64 && dtype != GCP_BF16)
+        return set_error(GCP_ERR_INVALID_ARG, "dtype must be GCP_F32, GCP_F64 or GCP_BF16");
+    if (!state) return set_error(GCP_ERR_INVALID_ARG, "state is NULL");
+    if (P > 0 && (!A || !G || !B || !C)) return set_error(GCP_ERR_INVALID_ARG, "A, G, B and C must be non-NULL");
+    if (dtype == GCP_BF16 && P > 0 && !A_master)
+        return set_error(GCP_ERR_INVALID_ARG, "GCP_BF16 needs the float master copy A_master");
+    if (eps_mode != GCP_EPS_INSIDE_SQRT && eps_mode != GCP_EPS_OUTSIDE_SQRT)
+        return set_error(GCP_ERR_INVALID_ARG, "eps_mode is not a gcp_eps_mode");
+    if (!(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0))
+        return set_error(GCP_ERR_INVALID_ARG, "beta1 and beta2 must be in [0, 1)");
+    if (!(eps >= 0.0) || !(alpha >= 0.0)) return set_error(GCP_ERR_INVALID_ARG, "alpha and eps must be >= 0");
+    return launch_adam(P, dtype, A, A_master, G, B, C, state, alpha, beta1, beta2, eps, lower, eps_mode, stream);
+}
+
+}  // extern "C"

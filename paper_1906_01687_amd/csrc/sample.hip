@@ -1,0 +1,361 @@
+// sample.hip -- index draws of the sampled GCP gradient (Kolda & Hong,
+// Sec. 4.1-4.3, Alg. 1-3): uniform draws, nonzero picks, semi-stratified
+// "zeros", and stratified zeros by rejection against a hash of the nonzeros.
+//
+// The rejection loop of Alg. 2 keeps drawing until q zeros are accepted.  On
+// the GPU the candidates j = 0, 1, 2, ... are examined in tiles of 1024; an
+// ordered compaction (per-tile counts, one scan, per-tile ballot ranks) keeps
+// exactly the first q accepted in counter order, and a one-workgroup refill
+// kernel continues the counter stream on the device in the rare case the
+// first batch holds fewer than q zeros.
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "device.hpp"
+
+namespace gcp {
+
+// ---------------------------------------------------------------------------
+// Nonzero hash build (CAS insert of key+1, linear probing).
+// ---------------------------------------------------------------------------
+__global__ void fill_u64_kernel(uint64_t* __restrict__ p, int64_t n, uint64_t v) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = v;
+}
+
+template <int D>
+__global__ void nz_build_kernel(const uint32_t* __restrict__ coo, int64_t nnz, Dims dims,
+                                unsigned long long* __restrict__ keys, uint32_t* __restrict__ pos,
+                                uint64_t mask) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t i[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) i[k] = coo[e * D + k];
+        const uint64_t L = linear_key<D>(i, dims.n);
+        const unsigned long long want = L + 1;
+        uint64_t h = mix64(L) & mask;
+        for (uint64_t probe = 0; probe <= mask; ++probe) {
+            const unsigned long long old = atomicCAS(&keys[h], 0ull, want);
+            if (old == 0ull || old == want) {
+                pos[h] = (uint32_t)e;
+                break;
+            }
+            h = (h + 1) & mask;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Direct draws: uniform, nonzero picks, semi-stratified zeros.
+// ---------------------------------------------------------------------------
+struct DirectArgs {
+    Dims dims;
+    uint64_t seed, pid, iter;
+    int kind;
+    int format;
+    int64_t count, out_off, nnz;
+    const void* values;
+    const uint32_t* coo;
+    NzTable tab;
+    uint32_t* idx;
+    void* xval;
+    uint8_t* stratum;
+    uint8_t nz_code;
+};
+
+template <int D, typename VT>
+__global__ void sample_direct_kernel(DirectArgs a) {
+    const VT* __restrict__ vals = static_cast<const VT*>(a.values);
+    VT* __restrict__ xout = static_cast<VT*>(a.xval);
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < a.count;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t i[D];
+        VT x = VT(0);
+        uint8_t code;
+        if (a.kind == kKindNonzero) {
+            const uint64_t e = draw_nonzero(a.seed, a.pid, (uint64_t)c, a.iter, (uint64_t)a.nnz);
+#pragma unroll
+            for (int k = 0; k < D; ++k) i[k] = a.coo[e * D + k];
+            x = vals[e];
+            code = a.nz_code;
+        } else {
+            draw_index<D>(a.seed, a.pid, (uint64_t)c, a.iter, kPurposeUniform, a.dims.n, i);
+            if (a.kind == kKindUniform) {
+                const uint64_t L = linear_key<D>(i, a.dims.n);
+                if (a.format == GCP_DENSE) {
+                    x = vals[L];
+                } else {
+                    const int64_t e = nz_find(a.tab, L);
+                    x = e >= 0 ? vals[e] : VT(0);
+                }
+                code = GCP_STRATUM_UNIFORM;
+            } else {
+                code = GCP_STRATUM_SEMI_ZERO;
+            }
+        }
+        const int64_t o = a.out_off + c;
+#pragma unroll
+        for (int k = 0; k < D; ++k) a.idx[o * D + k] = i[k];
+        xout[o] = x;
+        a.stratum[o] = code;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Rejection pipeline for stratified zeros.
+// Candidate j of tile b is j = b * 1024 + item * 256 + tid (item-major), so a
+// wave ballot per item ranks accepted candidates in counter order.
+// ---------------------------------------------------------------------------
+struct RejArgs {
+    Dims dims;
+    uint64_t seed, pid, iter;
+    int64_t ncand;  // candidates in the first batch
+    int64_t q;      // zeros wanted
+    int64_t p_off;  // output offset of zero 0
+    NzTable tab;
+    uint32_t* idx;
+    void* xval;
+    uint8_t* stratum;
+    int vdtype;
+    uint32_t* block_count;
+    uint64_t* block_offset;
+    uint64_t* total;
+    uint32_t* status;
+};
+
+template <int D>
+__device__ __forceinline__ bool candidate_accepted(const RejArgs& a, uint64_t j, uint32_t (&i)[D]) {
+    draw_index<D>(a.seed, a.pid, j, a.iter, kPurposeCandidate, a.dims.n, i);
+    return nz_find(a.tab, linear_key<D>(i, a.dims.n)) < 0;
+}
+
+template <int D>
+__global__ __launch_bounds__(kRejThreads) void rej_count_kernel(RejArgs a) {
+    __shared__ uint32_t wave_cnt[kRejThreads / kWave];
+    const int tid = threadIdx.x;
+    const uint64_t base = (uint64_t)blockIdx.x * kRejTile;
+    uint32_t mine = 0;
+#pragma unroll
+    for (int it = 0; it < kRejItems; ++it) {
+        const uint64_t j = base + (uint64_t)it * kRejThreads + tid;
+        uint32_t i[D];
+        if (j < (uint64_t)a.ncand && candidate_accepted<D>(a, j, i)) ++mine;
+    }
+    // wave sum then block sum
+    for (int o = kWave / 2; o > 0; o >>= 1) mine += __shfl_xor(mine, o);
+    if ((tid & (kWave - 1)) == 0) wave_cnt[tid / kWave] = mine;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < kRejThreads / kWave; ++w) t += wave_cnt[w];
+        a.block_count[blockIdx.x] = t;
+    }
+}
+
+// Exclusive scan of the per-tile counts by one workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void rej_scan_kernel(RejArgs a, int64_t nblk) {
+    __shared__ uint64_t part[1024];
+    __shared__ uint64_t carry;
+    const int tid = threadIdx.x;
+    if (tid == 0) carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < nblk; base += 1024) {
+        const int64_t b = base + tid;
+        const uint64_t v = b < nblk ? a.block_count[b] : 0;
+        part[tid] = v;
+        __syncthreads();
+        // Hillis-Steele inclusive scan in LDS
+        for (int o = 1; o < 1024; o <<= 1) {
+            const uint64_t add = tid >= o ? part[tid - o] : 0;
+            __syncthreads();
+            part[tid] += add;
+            __syncthreads();
+        }
+        if (b < nblk) a.block_offset[b] = carry + part[tid] - v;
+        __syncthreads();
+        if (tid == 1023) carry += part[1023];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        a.total[0] = carry;
+        a.status[0] = 0;
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void write_zero(const RejArgs& a, uint64_t rank, const uint32_t (&i)[D]) {
+    const int64_t o = a.p_off + (int64_t)rank;
+#pragma unroll
+    for (int k = 0; k < D; ++k) a.idx[o * D + k] = i[k];
+    if (a.xval) {
+        if (a.vdtype == GCP_F64) static_cast<double*>(a.xval)[o] = 0.0;
+        else static_cast<float*>(a.xval)[o] = 0.0f;
+    }
+    if (a.stratum) a.stratum[o] = GCP_STRATUM_ZERO;
+}
+
+// Block-wide exclusive ranks of accepted flags, in item-major candidate order.
+template <int D>
+__device__ __forceinline__ uint64_t rank_and_write(const RejArgs& a, uint64_t tile_first_rank,
+                                                   uint64_t base, uint64_t limit,
+                                                   uint32_t* wave_cnt) {
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = tid / kWave;
+    uint64_t running = tile_first_rank;
+    for (int it = 0; it < kRejItems; ++it) {
+        const uint64_t j = base + (uint64_t)it * kRejThreads + tid;
+        uint32_t i[D];
+        const bool acc = j < limit && candidate_accepted<D>(a, j, i);
+        const uint64_t bal = __ballot(acc);
+        const uint32_t before = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) wave_cnt[wave] = __popcll(bal);
+        __syncthreads();
+        uint64_t wave_base = 0, item_total = 0;
+        for (int w = 0; w < kRejThreads / kWave; ++w) {
+            if (w < wave) wave_base += wave_cnt[w];
+            item_total += wave_cnt[w];
+        }
+        const uint64_t rank = running + wave_base + before;
+        if (acc && rank < (uint64_t)a.q) write_zero<D>(a, rank, i);
+        running += item_total;
+        __syncthreads();
+    }
+    return running;
+}
+
+template <int D>
+__global__ __launch_bounds__(kRejThreads) void rej_write_kernel(RejArgs a) {
+    __shared__ uint32_t wave_cnt[kRejThreads / kWave];
+    const uint64_t first = a.block_offset[blockIdx.x];
+    if (first >= (uint64_t)a.q) return;  // block-uniform exit
+    rank_and_write<D>(a, first, (uint64_t)blockIdx.x * kRejTile, (uint64_t)a.ncand, wave_cnt);
+}
+
+// Continues the candidate stream after the first batch until q zeros exist.
+// Every thread of the single workgroup sees the same `filled` and exits together.
+template <int D>
+__global__ __launch_bounds__(kRejThreads) void rej_refill_kernel(RejArgs a) {
+    __shared__ uint32_t wave_cnt[kRejThreads / kWave];
+    uint64_t filled = a.total[0];
+    if (filled >= (uint64_t)a.q) return;
+    uint64_t base = (uint64_t)a.ncand;
+    for (int64_t t = 0; t < kRejMaxRefillTiles && filled < (uint64_t)a.q; ++t) {
+        filled = rank_and_write<D>(a, filled, base, ~0ull, wave_cnt);
+        base += kRejTile;
+    }
+    if (threadIdx.x == 0 && filled < (uint64_t)a.q) a.status[0] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+static Dims make_dims(const gcp_tensor* X) {
+    Dims d{};
+    for (int k = 0; k < X->d; ++k) d.n[k] = X->dims[k];
+    return d;
+}
+
+static NzTable make_table(const void* table, int64_t slots) {
+    NzTable t{};
+    if (table && slots > 0) {
+        t.keys = static_cast<const uint64_t*>(table);
+        t.pos = reinterpret_cast<const uint32_t*>(static_cast<const char*>(table) + 8 * slots);
+        t.mask = (uint64_t)slots - 1;
+    }
+    return t;
+}
+
+static int grid_for(int64_t n, int threads, int cap = 8192) {
+    int64_t b = (n + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (int)b;
+}
+
+gcp_status launch_nz_build(const gcp_tensor* X, void* table, int64_t slots, hipStream_t s) {
+    auto* keys = static_cast<unsigned long long*>(table);
+    auto* pos = reinterpret_cast<uint32_t*>(static_cast<char*>(table) + 8 * slots);
+    // keys and positions are cleared with a fill kernel (graph-capture safe)
+    fill_u64_kernel<<<grid_for(slots + (slots + 1) / 2, 256), 256, 0, s>>>(
+        static_cast<uint64_t*>(table), slots + (slots + 1) / 2, 0ull);
+    if (X->nnz > 0) {
+        const int g = grid_for(X->nnz, 256);
+        const Dims dims = make_dims(X);
+        dispatch_d(X->d, [&](auto dc) {
+            constexpr int D = decltype(dc)::value;
+            hipLaunchKernelGGL(nz_build_kernel<D>, dim3(g), dim3(256), 0, s, X->coo_idx, X->nnz, dims,
+                               keys, pos, (uint64_t)slots - 1);
+        });
+    }
+    return check_launch("gcp_nz_index_build");
+}
+
+template <int D>
+static void direct_launch(const DirectArgs& a, int vdtype, hipStream_t s) {
+    const int g = grid_for(a.count, 256);
+    if (vdtype == GCP_F64) hipLaunchKernelGGL((sample_direct_kernel<D, double>), dim3(g), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((sample_direct_kernel<D, float>), dim3(g), dim3(256), 0, s, a);
+}
+
+gcp_status launch_sample_direct(const gcp_tensor* X, const gcp_sampling* cfg, int kind, int64_t count,
+                                int64_t out_off, uint32_t* idx, void* xval, uint8_t* stratum,
+                                hipStream_t s) {
+    if (count <= 0) return GCP_OK;
+    DirectArgs a{};
+    a.dims = make_dims(X);
+    a.seed = cfg->seed;
+    a.pid = cfg->problem_id;
+    a.iter = cfg->iteration;
+    a.kind = kind;
+    a.format = X->format;
+    a.count = count;
+    a.out_off = out_off;
+    a.nnz = X->nnz;
+    a.values = X->values;
+    a.coo = X->coo_idx;
+    a.tab = make_table(X->nz_table, X->nz_slots);
+    a.idx = idx;
+    a.xval = xval;
+    a.stratum = stratum;
+    a.nz_code = cfg->sampler == GCP_SAMPLER_SEMI_STRATIFIED ? GCP_STRATUM_NZ_CORR : GCP_STRATUM_NZ;
+    dispatch_d(X->d, [&](auto dc) { direct_launch<decltype(dc)::value>(a, X->vdtype, s); });
+    return check_launch("gcp_sample");
+}
+
+template <int D>
+static void rejection_launch(const RejArgs& a, int64_t nblk, hipStream_t s) {
+    hipLaunchKernelGGL(rej_count_kernel<D>, dim3((unsigned)nblk), dim3(kRejThreads), 0, s, a);
+    hipLaunchKernelGGL(rej_scan_kernel, dim3(1), dim3(1024), 0, s, a, nblk);
+    hipLaunchKernelGGL(rej_write_kernel<D>, dim3((unsigned)nblk), dim3(kRejThreads), 0, s, a);
+    hipLaunchKernelGGL(rej_refill_kernel<D>, dim3(1), dim3(kRejThreads), 0, s, a);
+}
+
+gcp_status launch_rejection(const gcp_tensor* X, const gcp_sampling* cfg, int64_t ncand,
+                            const RejScratch& rs, uint32_t* idx_out, int64_t p_off, void* xval,
+                            uint8_t* stratum, hipStream_t s) {
+    if (cfg->q <= 0) return GCP_OK;
+    RejArgs a{};
+    a.dims = make_dims(X);
+    a.seed = cfg->seed;
+    a.pid = cfg->problem_id;
+    a.iter = cfg->iteration;
+    a.ncand = ncand;
+    a.q = cfg->q;
+    a.p_off = p_off;
+    a.tab = make_table(X->nz_table, X->nz_slots);
+    a.idx = idx_out;
+    a.xval = xval;
+    a.stratum = stratum;
+    a.vdtype = X->vdtype;
+    a.block_count = rs.block_count;
+    a.block_offset = rs.block_offset;
+    a.total = rs.total;
+    a.status = rs.status;
+    dispatch_d(X->d, [&](auto dc) { rejection_launch<decltype(dc)::value>(a, rs.nblk, s); });
+    return check_launch("stratified rejection");
+}
+
+}  // namespace gcp

@@ -1,0 +1,126 @@
+"""Host-only checks of the C-ABI library: it loads, exports every function that
+include/gcp.h declares, and its host-side queries and argument checks behave
+(no kernel is launched without a GPU)."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gcp.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gcp_[a-z0-9_]+)\s*\(", text)))
+
+
+def _lib():
+    from paper_1906_01687_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libgcp.so not built")
+    return _lib
+
+
+def test_every_declared_symbol_is_exported():
+    m = _lib()
+    raw = ctypes.CDLL(m.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 13
+    missing = [n for n in names if not hasattr(raw, n)]
+    assert not missing, missing
+    assert sorted(m.EXPORTS) == names
+
+
+def test_struct_layouts_match_header():
+    m = _lib()
+    assert ctypes.sizeof(m.GcpTensor) == 120
+    assert ctypes.sizeof(m.GcpFactors) == 80
+    assert ctypes.sizeof(m.GcpSampling) == 64
+
+
+def test_host_queries():
+    m = _lib()
+    L = m.lib()
+    assert L.gcp_abi_version() == 1
+    assert L.gcp_nz_table_slots(0) == 64
+    assert L.gcp_nz_table_slots(959756) == 1 << 21
+    s = L.gcp_nz_table_slots(5_000_000)
+    assert s >= 10_000_000 and s & (s - 1) == 0
+    assert L.gcp_nz_table_bytes(1 << 21) == 12 << 21
+
+
+def _dense_struct(m, dims, values=0x1000):
+    t = m.GcpTensor()
+    t.d = len(dims)
+    t.format = m.DENSE
+    t.vdtype = m.F32
+    for k, n in enumerate(dims):
+        t.dims[k] = n
+    t.values = values
+    return t
+
+
+def test_argument_errors_are_reported_without_launching():
+    m = _lib()
+    L = m.lib()
+    t = _dense_struct(m, (30, 40, 50))
+    cfg = m.GcpSampling()
+    cfg.sampler = m.STRATIFIED          # needs a COO tensor
+    cfg.p, cfg.q = 10, 10
+    st = L.gcp_sample(ctypes.byref(t), ctypes.byref(cfg), 0x10, 0x10, 0x10, None, 0, None)
+    assert st == 1 and b"COO" in L.gcp_last_error()
+    t.d = 9
+    cfg.sampler = m.UNIFORM
+    cfg.s = 5
+    assert L.gcp_sample(ctypes.byref(t), ctypes.byref(cfg), 0x10, 0x10, 0x10, None, 0, None) == 1
+    t = _dense_struct(m, (1 << 32, 2))
+    assert L.gcp_sample(ctypes.byref(t), ctypes.byref(cfg), 0x10, 0x10, 0x10, None, 0, None) == 1
+    t = _dense_struct(m, (1 << 31, 1 << 31, 4))
+    assert L.gcp_sample(ctypes.byref(t), ctypes.byref(cfg), 0x10, 0x10, 0x10, None, 0, None) == 2
+    # rank above the supported maximum
+    t = _dense_struct(m, (3, 4))
+    M = m.GcpFactors()
+    M.dtype = m.F32
+    M.rank = 65
+    M.A[0] = M.A[1] = 0x1000
+    G = (ctypes.c_void_p * 2)(0x1000, 0x1000)
+    st = L.gcp_sampled_grad(0, ctypes.byref(t), ctypes.byref(M), ctypes.byref(cfg), 1e-10, G, None,
+                            0x1000, 1 << 20, None)
+    assert st == 2
+    # workspace too small
+    M.rank = 4
+    need = L.gcp_sampled_grad_workspace_bytes(ctypes.byref(t), ctypes.byref(M), ctypes.byref(cfg))
+    assert need >= (3 + 4) * 4 * 8
+    st = L.gcp_sampled_grad(0, ctypes.byref(t), ctypes.byref(M), ctypes.byref(cfg), 1e-10, G, None,
+                            0x1000, need - 1, None)
+    assert st == 4 and b"workspace" in L.gcp_last_error()
+    # Adam argument checks
+    st = L.gcp_adam_step(10, m.BF16, 0x10, None, 0x10, 0x10, 0x10, 0x10, 0.01, 0.9, 0.999, 1e-8,
+                         -math.inf, 0, None)
+    assert st == 1 and b"master" in L.gcp_last_error()
+    st = L.gcp_adam_step(10, m.F32, 0x10, None, 0x10, 0x10, 0x10, 0x10, 0.01, 1.0, 0.999, 1e-8,
+                         -math.inf, 0, None)
+    assert st == 1
+
+
+def test_stratified_workspace_covers_rejection_scratch():
+    m = _lib()
+    L = m.lib()
+    t = m.GcpTensor()
+    t.d, t.format, t.vdtype = 3, m.COO, m.F32
+    for k, n in enumerate((1000, 800, 600)):
+        t.dims[k] = n
+    t.nnz = 959756
+    cfg = m.GcpSampling()
+    cfg.sampler, cfg.p, cfg.q = m.STRATIFIED, 100_000, 100_000
+    ws = L.gcp_sample_workspace_bytes(ctypes.byref(t), ctypes.byref(cfg))
+    nblk = math.ceil(math.ceil(1.1 * 1e5 * 4.8e8 / (4.8e8 - 959756)) / 1024)
+    assert ws >= nblk * 12
+    M = m.GcpFactors()
+    M.dtype, M.rank = m.F32, 8
+    ws2 = L.gcp_sampled_grad_workspace_bytes(ctypes.byref(t), ctypes.byref(M), ctypes.byref(cfg))
+    assert ws2 >= ws + 2400 * 8 * 8 + 100_000 * 3 * 4

@@ -1,0 +1,268 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars: sample indices, values and strata bit-exact; FP64 factors -> gradients
+within 1e-12 (relative Frobenius per mode); FP32 factors -> within 1e-5;
+Adam -> within the same bars.  Every case prints its name before it runs.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+import paper_1906_01687_amd as gcp
+from gpu_cases import (cfg_for, oracle_grad, oracle_samples, rel_fro, small_dense, small_sparse,
+                       to_device)
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+def announce(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def u32(t):
+    return t.to(torch.int64).cpu().numpy() & 0xFFFFFFFF
+
+
+def check_samples(pb, smp_gpu, smp_orc):
+    idx, xval, st = smp_gpu
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(u32(idx), smp_orc.idx)
+    np.testing.assert_array_equal(st.cpu().numpy().astype(np.int32), smp_orc.stratum)
+    np.testing.assert_array_equal(xval.to(torch.float64).cpu().numpy(), smp_orc.xval)
+
+
+# ---------------------------------------------------------------------------
+# sampling: bit-exact indices
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("it", [0, 7])
+def test_sample_uniform_dense_workload(it):
+    announce(f"sample uniform dense 30x40x50 f64 it={it}")
+    pb = to_device(synth.dense_gaussian_30x40x50())
+    check_samples(pb, gcp.sample(pb.X, cfg_for(pb, iteration=it)), oracle_samples(pb, iteration=it))
+
+
+@pytest.mark.parametrize("dims", [(13, 17, 11), (5, 9), (7, 3, 4, 6, 5), (1000,), (3, 2, 4, 2, 3, 2, 2, 3)])
+def test_sample_uniform_dense_shapes(dims):
+    announce(f"sample uniform dense {dims}")
+    pb = to_device(small_dense(dims=dims, rank=3, s=2049))
+    check_samples(pb, gcp.sample(pb.X, cfg_for(pb, iteration=3, problem_id=5)),
+                  oracle_samples(pb, iteration=3, problem_id=5))
+
+
+def test_sample_uniform_coo_lookup():
+    announce("sample uniform on COO (hash value lookup)")
+    w = small_sparse("counts", dims=(9, 8, 7), p=0, q=0)
+    w.sampler, w.s = synth.UNIFORM, 5000
+    pb = to_device(w)
+    smp = oracle_samples(pb, iteration=2)
+    assert np.count_nonzero(smp.xval) > 100
+    check_samples(pb, gcp.sample(pb.X, cfg_for(pb, iteration=2)), smp)
+
+
+@pytest.mark.parametrize("p,q", [(2111, 3333), (0, 1025), (1024, 0), (1, 1), (64, 65537)])
+def test_sample_stratified(p, q):
+    announce(f"sample stratified p={p} q={q}")
+    pb = to_device(small_sparse("binary", p=p, q=q))
+    for it in (0, 11):
+        check_samples(pb, gcp.sample(pb.X, cfg_for(pb, iteration=it)), oracle_samples(pb, iteration=it))
+
+
+@pytest.mark.parametrize("rho", [0.01, 0.5, 1.0, 3.0])
+def test_sample_stratified_refill_independent_of_rho(rho):
+    announce(f"sample stratified rho={rho} (device-side refill)")
+    w = small_sparse("binary", dims=(20, 19, 18), p=100, q=5000)
+    pb = to_device(w)
+    smp = oracle_samples(pb, iteration=4)
+    check_samples(pb, gcp.sample(pb.X, cfg_for(pb, iteration=4, rho=rho)), smp)
+
+
+def test_sample_stratified_dense_nonzeros():
+    announce("sample stratified, 60% nonzeros (many rejections)")
+    w = small_sparse("binary", dims=(12, 10, 9), p=300, q=4000)
+    w2 = synth.sparse_binary((12, 10, 9), 7, 0.6, seed=77, subsample=20000)
+    w.coo_idx, w.coo_val = w2[0], w2[1]
+    pb = to_device(w)
+    smp = oracle_samples(pb, iteration=1)
+    assert smp.examined > 1.5 * 4000
+    check_samples(pb, gcp.sample(pb.X, cfg_for(pb, iteration=1)), smp)
+
+
+@pytest.mark.parametrize("dims", [(61, 47, 33), (30, 7, 11, 13), (6, 5, 4, 3, 7)])
+def test_sample_semi_stratified(dims):
+    announce(f"sample semi-stratified {dims}")
+    pb = to_device(small_sparse("counts", dims=dims, p=1500, q=2500))
+    check_samples(pb, gcp.sample(pb.X, cfg_for(pb, iteration=9)), oracle_samples(pb, iteration=9))
+
+
+# ---------------------------------------------------------------------------
+# derivative and MTTKRP, unfused ABI path
+# ---------------------------------------------------------------------------
+
+def _unfused(pb, cfg):
+    idx, xval, st = gcp.sample(pb.X, cfg)
+    y, fs = gcp.loss_grad(pb.w.loss, pb.X, cfg, pb.M, idx, xval, st, with_loss=True)
+    G = gcp.mttkrp(pb.X, pb.M, idx, y)
+    return idx, y, fs, G
+
+
+CASES = [
+    ("dense_30x40x50_f64", lambda: synth.dense_gaussian_30x40x50()),
+    ("dense_f32_r5", lambda: small_dense()),
+    ("dense_f32_poisson_r10", lambda: small_dense(rank=10, loss=synth.POISSON)),
+    ("dense_f32_bernoulli_r1", lambda: small_dense(rank=1, loss=synth.BERNOULLI_ODDS)),
+    ("binary_strat_r7", lambda: small_sparse("binary")),
+    ("binary_semi_r8", lambda: small_sparse("binary", rank=8, sampler=synth.SEMI_STRATIFIED)),
+    ("counts_semi_r10", lambda: small_sparse("counts", rank=10)),
+    ("counts_strat_r33", lambda: small_sparse("counts", rank=33, sampler=synth.STRATIFIED)),
+    ("counts_semi_r64_d4", lambda: small_sparse("counts", dims=(30, 7, 11, 13), rank=64)),
+    ("dense_f32_d5_r16", lambda: small_dense(dims=(7, 3, 4, 6, 5), rank=16, s=1111)),
+    ("dense_f64_d2_r2", lambda: small_dense(dims=(40, 31), rank=2, s=777, dtype="f64")),
+]
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_unfused_parity(name, make):
+    announce(f"unfused sample->loss_grad->mttkrp {name}")
+    w = make()
+    pb = to_device(w)
+    cfg = cfg_for(pb, iteration=5)
+    idx, y, fs, G = _unfused(pb, cfg)
+    smp = oracle_samples(pb, iteration=5)
+    Gref, Fref, yref = oracle_grad(pb, smp)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(u32(idx), smp.idx)
+    tol = TOL[w.dtype]
+    yg = y.to(torch.float64).cpu().numpy()
+    assert np.linalg.norm(yg - yref) <= tol * np.linalg.norm(yref)
+    assert abs(fs.item() - Fref) <= tol * max(1.0, abs(Fref)) * 10
+    errs = rel_fro(G, Gref)
+    assert max(errs) <= tol, errs
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_fused_parity(name, make):
+    announce(f"fused gcp_sampled_grad {name}")
+    w = make()
+    pb = to_device(w)
+    for it in (0, 3):
+        cfg = cfg_for(pb, iteration=it)
+        G, fs = gcp.sampled_grad(w.loss, pb.X, pb.M, cfg, with_loss=True)
+        smp = oracle_samples(pb, iteration=it)
+        Gref, Fref, _ = oracle_grad(pb, smp)
+        torch.cuda.synchronize()
+        tol = TOL[w.dtype]
+        errs = rel_fro(G, Gref)
+        assert max(errs) <= tol, (it, errs)
+        assert abs(fs.item() - Fref) <= 10 * tol * max(1.0, abs(Fref))
+
+
+def test_fused_bf16_storage():
+    announce("fused gcp_sampled_grad bf16 factors")
+    w = small_sparse("counts", dims=(30, 7, 11, 13), rank=16)
+    pb = to_device(w, dtype="bf16")
+    cfg = cfg_for(pb, iteration=2)
+    G = gcp.sampled_grad(w.loss, pb.X, pb.M, cfg)
+    smp = oracle_samples(pb, iteration=2)
+    Gref, _, _ = oracle_grad(pb, smp)          # oracle on the bf16-rounded values
+    torch.cuda.synchronize()
+    assert max(rel_fro(G, Gref)) <= 1e-5
+
+
+def test_empty_sample_sets():
+    announce("empty sample sets")
+    pb = to_device(small_dense(s=0))
+    G = gcp.sampled_grad(pb.w.loss, pb.X, pb.M, cfg_for(pb))
+    torch.cuda.synchronize()
+    assert all(float(g.abs().max()) == 0.0 for g in G)
+    pb = to_device(small_sparse("binary", p=0, q=0))
+    G = gcp.sampled_grad(pb.w.loss, pb.X, pb.M, cfg_for(pb))
+    idx, xval, st = gcp.sample(pb.X, cfg_for(pb))
+    torch.cuda.synchronize()
+    assert idx.shape[0] == 0 and all(float(g.abs().max()) == 0.0 for g in G)
+
+
+def test_mttkrp_accumulate():
+    announce("gcp_mttkrp accumulate flag")
+    pb = to_device(small_dense(rank=6))
+    cfg = cfg_for(pb, iteration=1)
+    idx, xval, st = gcp.sample(pb.X, cfg)
+    y = gcp.loss_grad(pb.w.loss, pb.X, cfg, pb.M, idx, xval, st)
+    G1 = [g.clone() for g in gcp.mttkrp(pb.X, pb.M, idx, y)]
+    G2 = gcp.mttkrp(pb.X, pb.M, idx, y, out=[g.clone() for g in G1], accumulate=True)
+    torch.cuda.synchronize()
+    for a, b in zip(G1, G2):
+        torch.testing.assert_close(b, 2 * a, rtol=1e-6, atol=0)
+
+
+# ---------------------------------------------------------------------------
+# Adam
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("eps_mode", [0, 1])
+def test_adam_steps(dtype, eps_mode):
+    announce(f"adam dtype={dtype} eps_mode={eps_mode}")
+    w = small_sparse("counts", rank=10, dtype="f32")
+    pb = to_device(w, dtype=dtype)
+    adam = gcp.Adam(pb.M, lr=0.01, lower=0.0, eps_mode=eps_mode)
+    A64 = np.concatenate([a.reshape(-1) for a in pb.A64])
+    if dtype == "bf16":   # the master copy is float32 of the original values
+        A64 = np.concatenate([np.float32(a).astype(np.float64).reshape(-1) for a in w.A_init])
+    B = np.zeros_like(A64)
+    C = np.zeros_like(A64)
+    call = gcp.SampledGrad(w.loss, pb.X, pb.M, cfg_for(pb))
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    for t in range(1, 4):
+        call(iteration=t)
+        gflat = call.gbuf
+        g_host = gflat.to(torch.float64).cpu().numpy()     # the GPU gradient, fed to both updates
+        A_before = A64.copy()
+        adam.step(gflat)
+        oracle.adam(A64, g_host, B, C, t, alpha=0.01, lower=0.0, eps_mode=eps_mode)
+        torch.cuda.synchronize()
+        assert int(adam.state[0].item()) == t and int(adam.state[1].item()) == 0
+        got = (pb.M.master if dtype == "bf16" else pb.M.flat).to(torch.float64).cpu().numpy()
+        # the step dA, relative Frobenius, as the acceptance bar states it
+        d_ref = A64 - A_before
+        d_got = got - A_before
+        err = np.linalg.norm(d_got - d_ref) / np.linalg.norm(d_ref)
+        assert err <= tol, (t, err)
+        if dtype == "bf16":
+            shadow = pb.M.flat.to(torch.float32).cpu().numpy()
+            want = pb.M.master.cpu().to(torch.bfloat16).to(torch.float32).numpy()
+            np.testing.assert_array_equal(shadow, want)
+        # continue both from the device values so every step is compared from one start
+        A64 = got.copy()
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("make", [synth.sparse_binary_1000x800x600, synth.sparse_count_6000x24x77x32],
+                         ids=["binary_1000x800x600", "counts_6000x24x77x32"])
+def test_full_size_workload(make):
+    w = make()
+    announce(f"full-size {w.name}: fused vs oracle, unfused indices bit-exact")
+    pb = to_device(w)
+    cfg = cfg_for(pb, iteration=1)
+    G = gcp.sampled_grad(w.loss, pb.X, pb.M, cfg)
+    Gg = [g.clone() for g in G]
+    idx, xval, st = gcp.sample(pb.X, cfg)
+    smp = oracle_samples(pb, iteration=1)
+    Gref, _, _ = oracle_grad(pb, smp)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(u32(idx), smp.idx)
+    np.testing.assert_array_equal(xval.to(torch.float64).cpu().numpy(), smp.xval)
+    errs = rel_fro(Gg, Gref)
+    print(f"[result] {w.name} rel err per mode {errs}", flush=True)
+    assert max(errs) <= 1e-5, errs
