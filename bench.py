@@ -3,8 +3,8 @@
 A step is one pass of the whole hot path over one fresh sample set: index
 draws (stratified: nonzero picks plus zeros by rejection), model entries,
 weighted loss derivatives, the MTTKRP scatter into every mode, and the Adam
-update -- the library's gcp_sampled_grad followed by gcp_adam_step, with all
-inputs resident in HBM.  The default workload is the sparse binary tensor
+update -- the library's gcp_sampled_adam_step, with all inputs resident in
+HBM.  The default workload is the sparse binary tensor
 1000x800x600 (about 1e6 nonzeros, rank 8, FP32 factors, Bernoulli-odds loss,
 stratified sampling p = q = 1e5).
 
@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--workload", default="sparse_binary_1000x800x600")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="bound on the oracle timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after timing, run one device copy of this many MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -47,8 +49,8 @@ def algorithmic_bytes(w) -> float:
     Per sample: d rows of r factor values (b_f each), a read-modify-write of d
     gradient rows of r values at 4 + 4 bytes (FP32 accumulation), and the data
     bytes its stratum reads: uniform dense x (b_v); nonzero pick a COO row
-    (4 d) plus its value (b_v); stratified zero its index row from the rejection
-    output (4 d); semi-stratified zero nothing.
+    (4 d) plus its value (b_v); stratified zero the 8-byte key of its
+    membership probe; semi-stratified zero nothing.
     """
     d, r = w.d, w.rank
     bf = {"f64": 8, "f32": 4, "bf16": 2}[w.dtype]
@@ -57,7 +59,7 @@ def algorithmic_bytes(w) -> float:
     per = d * r * bf + d * r * rmw
     if w.sampler == 0:
         return w.s * (per + bv)
-    zero_data = 4 * d if w.sampler == 1 else 0
+    zero_data = 8 if w.sampler == 1 else 0
     return w.p * (per + 4 * d + bv) + w.q * (per + zero_data)
 
 
@@ -107,14 +109,13 @@ def main():
     M = gcp.Factors(w.dims, w.rank, tdt, dev, init=w.A_init)
     sampler_name = {0: "uniform", 1: "stratified", 2: "semi_stratified"}[w.sampler]
     cfg = gcp.sampling(sampler_name, s=w.s, p=w.p, q=w.q, seed=w.seed)
-    grad = gcp.SampledGrad(w.loss, X, M, cfg)
     adam = gcp.Adam(M, lr=w.lr, lower=w.lower)
+    step_call = gcp.SampledAdamStep(w.loss, X, M, cfg, adam)
     torch.cuda.synchronize()
     print(f"[bench] {w.name}: {w.n_samples} samples/step, nnz={w.nnz}", file=sys.stderr, flush=True)
 
     def step(it):
-        grad(iteration=it)
-        adam.step(grad.gbuf)
+        step_call(iteration=it)
 
     for it in range(args.warmup):
         step(it)
@@ -141,6 +142,15 @@ def main():
     achieved = balg / (kernel_ms / 1e3) / 1e9
     print(f"[bench] step {ms_per_step * 1e3:.1f} us, gradient kernel {kernel_ms * 1e3:.1f} us "
           f"({kn.value} timed), {achieved:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
+
+    if args.copy_mib > 0:
+        n = args.copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -193,9 +193,11 @@ gcp_status gcp_loss_grad(gcp_loss loss, const gcp_tensor *X, const gcp_sampling 
  * Gks; Alg. 1-3 last loop): G_k(i_k, :) += ytilde_i * prod_{k' != k} A_k'(i_k', :).
  *   G[k]        out, dims[k] x rank row-major; F64 when M->dtype is GCP_F64,
  *               else F32.  Overwritten unless `accumulate` is non-zero.
- * Sums are accumulated in FP64 in the workspace
- * (gcp_mttkrp_workspace_bytes bytes) and rounded once into G. */
-size_t gcp_mttkrp_workspace_bytes(const gcp_tensor *X, const gcp_factors *M);
+ * Accumulation: each workgroup sums the modes whose rows fit in its LDS in
+ * FP64 and publishes one partial (rounded to FP32); the partials are summed
+ * in FP64 in a fixed order.  Longer modes are summed with FP64 device atomics.
+ * The workspace (gcp_mttkrp_workspace_bytes(X, M, S) bytes) holds both. */
+size_t gcp_mttkrp_workspace_bytes(const gcp_tensor *X, const gcp_factors *M, int64_t S);
 gcp_status gcp_mttkrp(const gcp_tensor *X, const gcp_factors *M, const uint32_t *idx,
                       const void *ytilde, int64_t S, void *const *G, int accumulate,
                       void *ws, size_t ws_bytes, hipStream_t stream);
@@ -212,6 +214,27 @@ size_t gcp_sampled_grad_workspace_bytes(const gcp_tensor *X, const gcp_factors *
 gcp_status gcp_sampled_grad(gcp_loss loss, const gcp_tensor *X, const gcp_factors *M,
                             const gcp_sampling *cfg, double eps, void *const *G,
                             double *loss_sum, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * gcp_sampled_adam_step -- one iteration of Alg. 4's inner loop: the
+ * stochastic gradient of gcp_sampled_grad followed by the Adam step of
+ * gcp_adam_step on all modes, with the gradient reduction and the update
+ * fused into one kernel.  Samples, gradient and update equal
+ * gcp_sampled_grad followed by gcp_adam_step up to floating-point order.
+ *   A          the flat parameter array updated by the step (dtype M->dtype,
+ *              sum_k n_k r values); M->A[k] must point at mode k's block of it
+ *              (A + offset_k), so the gradient is taken at the same A.
+ *   A_master, B, C, state, alpha, beta1, beta2, adam_eps, lower, eps_mode
+ *              as in gcp_adam_step.
+ *   G          nullable; when given, G[k] (nullable entries) receive the
+ *              gradient as in gcp_sampled_grad.
+ *   ws         gcp_sampled_grad_workspace_bytes(X, M, cfg) bytes. */
+gcp_status gcp_sampled_adam_step(gcp_loss loss, const gcp_tensor *X, const gcp_factors *M,
+                                 const gcp_sampling *cfg, double eps, void *A, float *A_master,
+                                 void *B, void *C, int64_t *state, double alpha, double beta1,
+                                 double beta2, double adam_eps, double lower,
+                                 gcp_eps_mode eps_mode, void *const *G, double *loss_sum,
+                                 void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * gcp_adam_step -- one Adam step with projection over P parameters at once

@@ -54,7 +54,8 @@ EXPORTS = [
     "gcp_last_error", "gcp_abi_version", "gcp_nz_table_slots", "gcp_nz_table_bytes",
     "gcp_nz_index_build", "gcp_sample_workspace_bytes", "gcp_sample", "gcp_loss_grad",
     "gcp_mttkrp_workspace_bytes", "gcp_mttkrp", "gcp_sampled_grad_workspace_bytes",
-    "gcp_sampled_grad", "gcp_adam_step", "gcp_timing_start", "gcp_timing_stop",
+    "gcp_sampled_grad", "gcp_sampled_adam_step", "gcp_adam_step", "gcp_timing_start",
+    "gcp_timing_stop",
 ]
 
 _lib = None
@@ -80,10 +81,12 @@ def lib() -> ctypes.CDLL:
         "gcp_sample_workspace_bytes": (sz, [T, S]),
         "gcp_sample": (st, [T, S, P, P, P, P, sz, P]),
         "gcp_loss_grad": (st, [ctypes.c_int, T, S, M, P, P, P, i64, dbl, P, P, P]),
-        "gcp_mttkrp_workspace_bytes": (sz, [T, M]),
+        "gcp_mttkrp_workspace_bytes": (sz, [T, M, i64]),
         "gcp_mttkrp": (st, [T, M, P, P, i64, P, ctypes.c_int, P, sz, P]),
         "gcp_sampled_grad_workspace_bytes": (sz, [T, M, S]),
         "gcp_sampled_grad": (st, [ctypes.c_int, T, M, S, dbl, P, P, P, sz, P]),
+        "gcp_sampled_adam_step": (st, [ctypes.c_int, T, M, S, dbl, P, P, P, P, P, dbl, dbl, dbl, dbl, dbl,
+                                       ctypes.c_int, P, P, P, sz, P]),
         "gcp_adam_step": (st, [i64, ctypes.c_int, P, P, P, P, P, P, dbl, dbl, dbl, dbl, dbl,
                                ctypes.c_int, P]),
         "gcp_timing_start": (st, [i64]),

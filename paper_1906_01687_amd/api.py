@@ -225,7 +225,7 @@ def mttkrp(X: DataTensor, M: Factors, idx, ytilde, out: Optional[List[torch.Tens
     if out is None:
         out = M.grad_views(M.grad_buffer())
     t, m = X.struct(), M.struct()
-    nbytes = int(L.gcp_mttkrp_workspace_bytes(ctypes.byref(t), ctypes.byref(m)))
+    nbytes = int(L.gcp_mttkrp_workspace_bytes(ctypes.byref(t), ctypes.byref(m), int(idx.shape[0])))
     ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=X.values.device)
     check(L.gcp_mttkrp(ctypes.byref(t), ctypes.byref(m), _ptr(idx), _ptr(ytilde), int(idx.shape[0]),
                        _ptr_array(out), int(bool(accumulate)), _ptr(ws), nbytes, _stream(stream)))
@@ -267,6 +267,35 @@ def sampled_grad(loss, X: DataTensor, M: Factors, cfg: GcpSampling, eps: float =
     call = SampledGrad(loss, X, M, cfg, eps, out, with_loss)
     G = call(stream=stream)
     return (G, call.loss_sum) if with_loss else G
+
+
+class SampledAdamStep:
+    """gcp_sampled_adam_step: sampled gradient and Adam update in one call (Alg. 4 inner loop)."""
+
+    def __init__(self, loss, X: DataTensor, M: Factors, cfg: GcpSampling, adam: "Adam",
+                 eps: float = LOSS_EPS, keep_grad: bool = False, with_loss: bool = False):
+        L = lib()
+        if adam.M is not M:
+            raise ValueError("adam must belong to the same Factors")
+        self.loss = _loss_code(loss)
+        self.X, self.M, self.cfg, self.adam, self.eps = X, M, cfg, adam, float(eps)
+        self.t, self.m = X.struct(), M.struct()
+        self.gbuf = M.grad_buffer() if keep_grad else None
+        self.out_ptrs = _ptr_array(M.grad_views(self.gbuf)) if keep_grad else None
+        self.nbytes = int(L.gcp_sampled_grad_workspace_bytes(ctypes.byref(self.t), ctypes.byref(self.m),
+                                                              ctypes.byref(cfg)))
+        self.ws = torch.empty(max(self.nbytes, 1), dtype=torch.uint8, device=X.values.device)
+        self.loss_sum = torch.zeros(1, dtype=torch.float64, device=X.values.device) if with_loss else None
+
+    def __call__(self, iteration: Optional[int] = None, stream=None) -> None:
+        if iteration is not None:
+            self.cfg.iteration = int(iteration)
+        a, M = self.adam, self.M
+        check(lib().gcp_sampled_adam_step(
+            self.loss, ctypes.byref(self.t), ctypes.byref(self.m), ctypes.byref(self.cfg), self.eps,
+            _ptr(M.flat), _ptr(M.master), _ptr(a.B), _ptr(a.C), _ptr(a.state), float(a.lr), float(a.beta1),
+            float(a.beta2), float(a.eps), float(a.lower), int(a.eps_mode), self.out_ptrs, _ptr(self.loss_sum),
+            _ptr(self.ws), self.nbytes, _stream(stream)))
 
 
 class Adam:

@@ -64,13 +64,26 @@ int64_t rejection_batch(const gcp_tensor* X, const gcp_sampling* cfg) {
 
 RejScratch carve_rejection(Carver& c, void* base, int64_t ncand) {
     RejScratch r{};
-    r.nblk = (ncand + kRejTile - 1) / kRejTile;
-    if (r.nblk < 1) r.nblk = 1;
-    r.block_count = c.take<uint32_t>(base, (size_t)r.nblk);
-    r.block_offset = c.take<uint64_t>(base, (size_t)r.nblk);
-    r.total = c.take<uint64_t>(base, 1);
+    r.nchunks = (ncand + kRejChunk - 1) / kRejChunk;
+    if (r.nchunks < 1) r.nchunks = 1;
+    r.chunk_count = c.take<uint32_t>(base, (size_t)r.nchunks);
+    r.chunk_prefix = c.take<uint64_t>(base, (size_t)r.nchunks + 1);
     r.status = c.take<uint32_t>(base, 1);
     return r;
+}
+
+int device_cu_count() {
+    static std::mutex mu;
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    std::lock_guard<std::mutex> lk(mu);
+    if (cache[dev] == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cache[dev] = n;
+    }
+    return cache[dev];
 }
 
 // ---------------------------------------------------------------------------
@@ -167,6 +180,59 @@ static size_t sample_ws(const gcp_tensor* X, const gcp_sampling* cfg, Carver& c,
     return c.bytes();
 }
 
+static gcp_status check_adam(gcp_dtype dtype, int64_t P, const void* A, const float* A_master, const void* B,
+                             const void* C, const int64_t* state, double alpha, double beta1, double beta2,
+                             double eps, gcp_eps_mode eps_mode) {
+    if (P < 0) return set_error(GCP_ERR_INVALID_ARG, "P must be >= 0");
+    if (dtype != GCP_F32 && dtype != GCP_F64 && dtype != GCP_BF16)
+        return set_error(GCP_ERR_INVALID_ARG, "dtype must be GCP_F32, GCP_F64 or GCP_BF16");
+    if (!state) return set_error(GCP_ERR_INVALID_ARG, "state is NULL");
+    if (P > 0 && (!A || !B || !C)) return set_error(GCP_ERR_INVALID_ARG, "A, B and C must be non-NULL");
+    if (dtype == GCP_BF16 && P > 0 && !A_master)
+        return set_error(GCP_ERR_INVALID_ARG, "GCP_BF16 needs the float master copy A_master");
+    if (eps_mode != GCP_EPS_INSIDE_SQRT && eps_mode != GCP_EPS_OUTSIDE_SQRT)
+        return set_error(GCP_ERR_INVALID_ARG, "eps_mode is not a gcp_eps_mode");
+    if (!(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0))
+        return set_error(GCP_ERR_INVALID_ARG, "beta1 and beta2 must be in [0, 1)");
+    if (!(eps >= 0.0) || !(alpha >= 0.0)) return set_error(GCP_ERR_INVALID_ARG, "alpha and eps must be >= 0");
+    return GCP_OK;
+}
+
+static size_t mttkrp_ws(const gcp_tensor* X, const gcp_factors* M, int64_t S, void* base, ScatterPlan* plan,
+                        double** acc, void** partials) {
+    const ScatterPlan pl = plan_scatter(X, M, (S + 63) / 64);
+    Carver c;
+    double* a = c.take<double>(base, (size_t)pl.acc_total);
+    void* p = c.take<char>(base, scatter_partials_bytes(pl, M->dtype));
+    if (plan) *plan = pl;
+    if (acc) *acc = a;
+    if (partials) *partials = p;
+    return c.bytes();
+}
+
+struct FusedLayout {
+    ScatterPlan plan;
+    int64_t ncand;
+    double* acc;
+    void* partials;
+    RejScratch rs;
+    bool rejection;
+};
+
+static size_t fused_ws(const gcp_tensor* X, const gcp_factors* M, const gcp_sampling* cfg, void* base,
+                       FusedLayout* out) {
+    FusedLayout f{};
+    f.rejection = cfg->sampler == GCP_SAMPLER_STRATIFIED && cfg->q > 0;
+    f.ncand = f.rejection ? rejection_batch(X, cfg) : 0;
+    f.plan = plan_scatter(X, M, fused_items(cfg, f.ncand));
+    Carver c;
+    f.acc = c.take<double>(base, (size_t)f.plan.acc_total);
+    f.partials = c.take<char>(base, scatter_partials_bytes(f.plan, M->dtype));
+    if (f.rejection) f.rs = carve_rejection(c, base, f.ncand);
+    if (out) *out = f;
+    return c.bytes();
+}
+
 // Kernel timing session (see gcp_timing_start in gcp.h).
 struct Timing {
     std::mutex mu;
@@ -185,6 +251,27 @@ static void timing_record(bool before, hipStream_t s) {
         (void)hipEventRecord(g_timing.stop[g_timing.used], s);
         ++g_timing.used;
     }
+}
+
+// The launch sequence shared by gcp_sampled_grad and gcp_sampled_adam_step.
+static gcp_status sampled_common(gcp_loss loss, const gcp_tensor* X, const gcp_factors* M, const gcp_sampling* cfg,
+                                 double eps, void* const* G, double* loss_sum, void* ws, size_t ws_bytes,
+                                 const AdamParams* adam, hipStream_t stream) {
+    const size_t need = fused_ws(X, M, cfg, nullptr, nullptr);
+    if (!ws || ws_bytes < need) return set_error(GCP_ERR_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
+    FusedLayout f{};
+    fused_ws(X, M, cfg, ws, &f);
+    if (f.rejection) {
+        if (gcp_status st = launch_rejection_count(X, cfg, f.ncand, f.rs, stream)) return st;
+    }
+    if (gcp_status st = launch_fill_zero(f.acc, f.plan.acc_total, stream)) return st;
+    timing_record(true, stream);
+    const gcp_status st = launch_grad_fused(loss, X, M, cfg, eps, f.plan, f.ncand,
+                                            f.rejection ? f.rs.chunk_prefix : nullptr, f.acc, f.partials,
+                                            loss_sum, stream);
+    timing_record(false, stream);
+    if (st) return st;
+    return launch_reduce(M, f.plan, f.acc, f.partials, G, 0, adam, stream);
 }
 
 }  // namespace gcp
@@ -239,7 +326,9 @@ gcp_status gcp_sample(const gcp_tensor* X, const gcp_sampling* cfg, uint32_t* id
     if (gcp_status st = launch_sample_direct(X, cfg, kKindNonzero, cfg->p, 0, idx, xval, stratum, stream)) return st;
     if (cfg->sampler == GCP_SAMPLER_SEMI_STRATIFIED)
         return launch_sample_direct(X, cfg, kKindSemiZero, cfg->q, cfg->p, idx, xval, stratum, stream);
-    return launch_rejection(X, cfg, rejection_batch(X, cfg), rs, idx, cfg->p, xval, stratum, stream);
+    const int64_t ncand = rejection_batch(X, cfg);
+    if (gcp_status st = launch_rejection_count(X, cfg, ncand, rs, stream)) return st;
+    return launch_rejection_write(X, cfg, ncand, rs, idx, cfg->p, xval, stratum, stream);
 }
 
 gcp_status gcp_loss_grad(gcp_loss loss, const gcp_tensor* X, const gcp_sampling* cfg, const gcp_factors* M,
@@ -257,11 +346,9 @@ gcp_status gcp_loss_grad(gcp_loss loss, const gcp_tensor* X, const gcp_sampling*
     return launch_loss_grad(loss, X, cfg, M, idx, xval, stratum, S, eps, ytilde, loss_sum, stream);
 }
 
-size_t gcp_mttkrp_workspace_bytes(const gcp_tensor* X, const gcp_factors* M) {
-    if (!X || !M || X->d < 1 || X->d > GCP_MAX_D) return 0;
-    Carver c;
-    c.take<double>(nullptr, (size_t)acc_layout(X, M).offset[X->d]);
-    return c.bytes();
+size_t gcp_mttkrp_workspace_bytes(const gcp_tensor* X, const gcp_factors* M, int64_t S) {
+    if (!X || !M || X->d < 1 || X->d > GCP_MAX_D || M->rank < 1 || S < 0) return 0;
+    return mttkrp_ws(X, M, S, nullptr, nullptr, nullptr, nullptr);
 }
 
 gcp_status gcp_mttkrp(const gcp_tensor* X, const gcp_factors* M, const uint32_t* idx, const void* ytilde, int64_t S,
@@ -274,33 +361,20 @@ gcp_status gcp_mttkrp(const gcp_tensor* X, const gcp_factors* M, const uint32_t*
     for (int k = 0; k < X->d; ++k)
         if (!G[k]) return set_error(GCP_ERR_INVALID_ARG, "G[" + std::to_string(k) + "] is NULL");
     if (S > 0 && (!idx || !ytilde)) return set_error(GCP_ERR_INVALID_ARG, "idx and ytilde must be non-NULL");
-    const size_t need = gcp_mttkrp_workspace_bytes(X, M);
+    const size_t need = gcp_mttkrp_workspace_bytes(X, M, S);
     if (!ws || ws_bytes < need) return set_error(GCP_ERR_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
-    const AccLayout L = acc_layout(X, M);
-    Carver c;
-    double* acc = c.take<double>(ws, (size_t)L.offset[X->d]);
-    if (gcp_status st = launch_fill_zero(acc, L.offset[X->d], stream)) return st;
-    if (gcp_status st = launch_mttkrp_list(X, M, idx, ytilde, S, acc, L, stream)) return st;
-    return launch_finalize(X, M, acc, L, G, accumulate, stream);
-}
-
-static size_t fused_ws(const gcp_tensor* X, const gcp_factors* M, const gcp_sampling* cfg, void* base, double** acc,
-                       uint32_t** zlist, RejScratch* rs) {
-    Carver c;
-    double* a = c.take<double>(base, (size_t)acc_layout(X, M).offset[X->d]);
-    if (acc) *acc = a;
-    if (cfg->sampler == GCP_SAMPLER_STRATIFIED && cfg->q > 0) {
-        uint32_t* z = c.take<uint32_t>(base, (size_t)cfg->q * (size_t)X->d);
-        if (zlist) *zlist = z;
-        RejScratch r = carve_rejection(c, base, rejection_batch(X, cfg));
-        if (rs) *rs = r;
-    }
-    return c.bytes();
+    ScatterPlan pl{};
+    double* acc = nullptr;
+    void* partials = nullptr;
+    mttkrp_ws(X, M, S, ws, &pl, &acc, &partials);
+    if (gcp_status st = launch_fill_zero(acc, pl.acc_total, stream)) return st;
+    if (gcp_status st = launch_grad_list(X, M, idx, ytilde, S, pl, acc, partials, stream)) return st;
+    return launch_reduce(M, pl, acc, partials, G, accumulate, nullptr, stream);
 }
 
 size_t gcp_sampled_grad_workspace_bytes(const gcp_tensor* X, const gcp_factors* M, const gcp_sampling* cfg) {
-    if (!X || !M || !cfg || X->d < 1 || X->d > GCP_MAX_D) return 0;
-    return fused_ws(X, M, cfg, nullptr, nullptr, nullptr, nullptr);
+    if (!X || !M || !cfg || X->d < 1 || X->d > GCP_MAX_D || M->rank < 1) return 0;
+    return fused_ws(X, M, cfg, nullptr, nullptr);
 }
 
 gcp_status gcp_sampled_grad(gcp_loss loss, const gcp_tensor* X, const gcp_factors* M, const gcp_sampling* cfg,
@@ -314,23 +388,43 @@ gcp_status gcp_sampled_grad(gcp_loss loss, const gcp_tensor* X, const gcp_factor
     if (!G) return set_error(GCP_ERR_INVALID_ARG, "G is NULL");
     for (int k = 0; k < X->d; ++k)
         if (!G[k]) return set_error(GCP_ERR_INVALID_ARG, "G[" + std::to_string(k) + "] is NULL");
-    const size_t need = gcp_sampled_grad_workspace_bytes(X, M, cfg);
-    if (!ws || ws_bytes < need) return set_error(GCP_ERR_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
-    double* acc = nullptr;
-    uint32_t* zlist = nullptr;
-    RejScratch rs{};
-    fused_ws(X, M, cfg, ws, &acc, &zlist, &rs);
-    const AccLayout L = acc_layout(X, M);
-    if (gcp_status st = launch_fill_zero(acc, L.offset[X->d], stream)) return st;
-    if (zlist) {
-        if (gcp_status st = launch_rejection(X, cfg, rejection_batch(X, cfg), rs, zlist, 0, nullptr, nullptr, stream))
-            return st;
+    return sampled_common(loss, X, M, cfg, eps, G, loss_sum, ws, ws_bytes, nullptr, stream);
+}
+
+gcp_status gcp_sampled_adam_step(gcp_loss loss, const gcp_tensor* X, const gcp_factors* M, const gcp_sampling* cfg,
+                                 double eps, void* A, float* A_master, void* B, void* C, int64_t* state,
+                                 double alpha, double beta1, double beta2, double adam_eps, double lower,
+                                 gcp_eps_mode eps_mode, void* const* G, double* loss_sum, void* ws,
+                                 size_t ws_bytes, hipStream_t stream) {
+    clear_error();
+    if (gcp_status st = check_loss(loss)) return st;
+    if (gcp_status st = check_tensor(X)) return st;
+    if (gcp_status st = check_sampling(X, cfg)) return st;
+    if (gcp_status st = check_factors(X, M)) return st;
+    int64_t P = 0;
+    for (int k = 0; k < X->d; ++k) P += X->dims[k] * M->rank;
+    if (gcp_status st = check_adam((gcp_dtype)M->dtype, P, A, A_master, B, C, state, alpha, beta1, beta2, adam_eps,
+                                   eps_mode))
+        return st;
+    // the gathers must read the very parameters the step updates: A_k = A + offset_k
+    const size_t esz = M->dtype == GCP_F64 ? 8 : (M->dtype == GCP_F32 ? 4 : 2);
+    int64_t off = 0;
+    for (int k = 0; k < X->d; ++k) {
+        if (M->A[k] != static_cast<const char*>(A) + off * esz)
+            return set_error(GCP_ERR_INVALID_ARG, "M->A[k] must be the mode-k block of the flat parameter array A");
+        off += X->dims[k] * M->rank;
     }
-    timing_record(true, stream);
-    const gcp_status st = launch_fused(loss, X, M, cfg, eps, zlist, acc, L, loss_sum, stream);
-    timing_record(false, stream);
-    if (st) return st;
-    return launch_finalize(X, M, acc, L, G, 0, stream);
+    const AdamParams ap{A, A_master, B, C, state, alpha, beta1, beta2, adam_eps, lower, (int)eps_mode};
+    return sampled_common(loss, X, M, cfg, eps, G, loss_sum, ws, ws_bytes, &ap, stream);
+}
+
+gcp_status gcp_adam_step(int64_t P, gcp_dtype dtype, void* A, float* A_master, const void* G, void* B, void* C,
+                         int64_t* state, double alpha, double beta1, double beta2, double eps, double lower,
+                         gcp_eps_mode eps_mode, hipStream_t stream) {
+    clear_error();
+    if (gcp_status st = check_adam(dtype, P, A, A_master, B, C, state, alpha, beta1, beta2, eps, eps_mode)) return st;
+    if (P > 0 && !G) return set_error(GCP_ERR_INVALID_ARG, "G must be non-NULL");
+    return launch_adam(P, dtype, A, A_master, G, B, C, state, alpha, beta1, beta2, eps, lower, eps_mode, stream);
 }
 
 gcp_status gcp_timing_start(int64_t max_launches) {
@@ -379,25 +473,6 @@ gcp_status gcp_timing_stop(double* total_ms, int64_t* launches) {
     g_timing.used = 0;
     g_timing.armed = false;
     return st;
-}
-
-gcp_status gcp_adam_step(int64_t P, gcp_dtype dtype, void* A, float* A_master, const void* G, void* B, void* C,
-                         int64_t* state, double alpha, double beta1, double beta2, double eps, double lower,
-                         gcp_eps_mode eps_mode, hipStream_t stream) {
-    clear_error();
-    if (P < 0) return set_error(GCP_ERR_INVALID_ARG, "P must be >= 0");
-    if (dtype != GCP_F32 && dtype != GCP_F64 && dtype != GCP_BF16)
-        return set_error(GCP_ERR_INVALID_ARG, "dtype must be GCP_F32, GCP_F64 or GCP_BF16");
-    if (!state) return set_error(GCP_ERR_INVALID_ARG, "state is NULL");
-    if (P > 0 && (!A || !G || !B || !C)) return set_error(GCP_ERR_INVALID_ARG, "A, G, B and C must be non-NULL");
-    if (dtype == GCP_BF16 && P > 0 && !A_master)
-        return set_error(GCP_ERR_INVALID_ARG, "GCP_BF16 needs the float master copy A_master");
-    if (eps_mode != GCP_EPS_INSIDE_SQRT && eps_mode != GCP_EPS_OUTSIDE_SQRT)
-        return set_error(GCP_ERR_INVALID_ARG, "eps_mode is not a gcp_eps_mode");
-    if (!(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0))
-        return set_error(GCP_ERR_INVALID_ARG, "beta1 and beta2 must be in [0, 1)");
-    if (!(eps >= 0.0) || !(alpha >= 0.0)) return set_error(GCP_ERR_INVALID_ARG, "alpha and eps must be >= 0");
-    return launch_adam(P, dtype, A, A_master, G, B, C, state, alpha, beta1, beta2, eps, lower, eps_mode, stream);
 }
 
 }  // extern "C"

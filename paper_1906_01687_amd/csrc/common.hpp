@@ -49,40 +49,76 @@ struct Carver {
     size_t bytes() const { return (off + 255) & ~size_t(255); }
 };
 
-// Rejection sampling of stratified zeros: 1024 candidates per block.
+// Rejection sampling of stratified zeros: candidates are counted per chunk of
+// 64 (one wave), chunk counts are scanned, then ranked per chunk.
+constexpr int kRejChunk = 64;
 constexpr int kRejThreads = 256;
-constexpr int kRejItems = 4;
-constexpr int kRejTile = kRejThreads * kRejItems;
 // Refill loop cap (tiles of 1024 candidates beyond the first batch).
 constexpr int64_t kRejMaxRefillTiles = int64_t(1) << 22;
 
 // Number of candidates in the first rejection batch.
 int64_t rejection_batch(const gcp_tensor* X, const gcp_sampling* cfg);
 
-// Scratch used by the rejection pipeline for a first batch of `ncand`.
+// Scratch of the rejection pipeline for a first batch of `ncand` candidates.
 struct RejScratch {
-    uint32_t* block_count;   // [nblk]
-    uint64_t* block_offset;  // [nblk]
-    uint64_t* total;         // [1] accepted in the first batch
+    uint32_t* chunk_count;   // [nchunks]
+    uint64_t* chunk_prefix;  // [nchunks + 1]: exclusive prefixes, then the total
     uint32_t* status;        // [1] 0 ok, 1 refill cap reached
-    int64_t nblk;
+    int64_t nchunks;
 };
 RejScratch carve_rejection(Carver& c, void* base, int64_t ncand);
+
+// Multiprocessor count of the current device (cached per device).
+int device_cu_count();
+
+// LDS bytes a gradient workgroup may use for privatised FP64 partials.
+constexpr int64_t kLdsBudgetBytes = 156 * 1024;
+
+// How a gradient launch scatters: which modes are privatised in LDS (and
+// where), which use device atomics, and the launch shape.
+struct ScatterPlan {
+    int d;
+    int64_t P;                          // sum_k n_k r
+    int64_t off[GCP_MAX_D + 1];         // flat element offset of mode k
+    uint32_t priv_mask;                 // bit k: mode k accumulated in LDS
+    int64_t lds_off[GCP_MAX_D];         // offset of mode k in the LDS partial (elements)
+    int64_t lds_total;                  // elements of one partial
+    int64_t acc_off[GCP_MAX_D];         // offset of mode k in the FP64 atomic accumulator
+    int64_t acc_total;
+    int64_t blocks;                     // gradient workgroups (= number of partials)
+    int threads;                        // threads per gradient workgroup
+};
+ScatterPlan plan_scatter(const gcp_tensor* X, const gcp_factors* M, int64_t n_items);
+size_t scatter_partials_bytes(const ScatterPlan& pl, int fdtype);
+int64_t fused_items(const gcp_sampling* cfg, int64_t ncand);
+
+struct AdamParams {
+    void* A;
+    float* A_master;
+    void* B;
+    void* C;
+    int64_t* state;
+    double alpha, beta1, beta2, eps, lower;
+    int eps_mode;
+};
 
 // Launchers (arguments already validated).
 gcp_status launch_nz_build(const gcp_tensor* X, void* table, int64_t slots, hipStream_t s);
 
-// Direct samples c in [first, first + count) of one kind, written at out_off.
+// Direct samples c in [0, count) of one kind, written at out_off.
 enum SampleKind { kKindUniform = 0, kKindNonzero = 1, kKindSemiZero = 2 };
 gcp_status launch_sample_direct(const gcp_tensor* X, const gcp_sampling* cfg, int kind,
                                 int64_t count, int64_t out_off, uint32_t* idx, void* xval,
                                 uint8_t* stratum, hipStream_t s);
 
-// Rejection pipeline: the first q accepted candidates' indices are written to
-// idx_out + (p_off + rank) * d; if xval/stratum are given they get 0 / ZERO.
-gcp_status launch_rejection(const gcp_tensor* X, const gcp_sampling* cfg, int64_t ncand,
-                            const RejScratch& rs, uint32_t* idx_out, int64_t p_off, void* xval,
-                            uint8_t* stratum, hipStream_t s);
+// Chunk counts and their scan for the first rejection batch.
+gcp_status launch_rejection_count(const gcp_tensor* X, const gcp_sampling* cfg, int64_t ncand,
+                                  const RejScratch& rs, hipStream_t s);
+// Writes the first q accepted candidates' indices at idx_out + (p_off + rank) * d
+// (xval/stratum get 0 / ZERO when given), including the device-side refill.
+gcp_status launch_rejection_write(const gcp_tensor* X, const gcp_sampling* cfg, int64_t ncand,
+                                  const RejScratch& rs, uint32_t* idx_out, int64_t p_off, void* xval,
+                                  uint8_t* stratum, hipStream_t s);
 
 // Stratum weights for X and cfg (omega/s, eta/p, zeta/q, eta/p, omega/q).
 void stratum_weights(const gcp_tensor* X, const gcp_sampling* cfg, double w[5]);
@@ -92,23 +128,22 @@ gcp_status launch_loss_grad(gcp_loss loss, const gcp_tensor* X, const gcp_sampli
                             const uint8_t* stratum, int64_t S, double eps, void* ytilde,
                             double* loss_sum, hipStream_t s);
 
-// FP64 accumulators for all modes: acc + offset[k], offset[d] = total.
-struct AccLayout {
-    int64_t offset[GCP_MAX_D + 1];
-};
-AccLayout acc_layout(const gcp_tensor* X, const gcp_factors* M);
-
 gcp_status launch_fill_zero(double* p, int64_t n, hipStream_t s);
-gcp_status launch_finalize(const gcp_tensor* X, const gcp_factors* M, const double* acc,
-                           const AccLayout& L, void* const* G, int accumulate, hipStream_t s);
 
-gcp_status launch_mttkrp_list(const gcp_tensor* X, const gcp_factors* M, const uint32_t* idx,
-                              const void* ytilde, int64_t S, double* acc, const AccLayout& L,
-                              hipStream_t s);
+gcp_status launch_grad_list(const gcp_tensor* X, const gcp_factors* M, const uint32_t* idx,
+                            const void* ytilde, int64_t S, const ScatterPlan& pl, double* acc,
+                            void* partials, hipStream_t s);
 
-gcp_status launch_fused(gcp_loss loss, const gcp_tensor* X, const gcp_factors* M,
-                        const gcp_sampling* cfg, double eps, const uint32_t* zero_list,
-                        double* acc, const AccLayout& L, double* loss_sum, hipStream_t s);
+gcp_status launch_grad_fused(gcp_loss loss, const gcp_tensor* X, const gcp_factors* M,
+                             const gcp_sampling* cfg, double eps, const ScatterPlan& pl, int64_t ncand,
+                             const uint64_t* chunk_prefix, double* acc, void* partials,
+                             double* loss_sum, hipStream_t s);
+
+// G[k] (nullable entries) from partials and accumulator; with adam != NULL the
+// Adam step is applied to the same elements in the same kernel.
+gcp_status launch_reduce(const gcp_factors* M, const ScatterPlan& pl, const double* acc,
+                         const void* partials, void* const* G, int accumulate, const AdamParams* adam,
+                         hipStream_t s);
 
 gcp_status launch_adam(int64_t P, gcp_dtype dtype, void* A, float* A_master, const void* G,
                        void* B, void* C, int64_t* state, double alpha, double beta1, double beta2,

@@ -111,6 +111,14 @@ __device__ __forceinline__ int64_t nz_find(const NzTable& t, uint64_t L) {
     return -1;
 }
 
+// Rejection candidate j (purpose 2): its indices, and whether X is zero there.
+template <int D>
+__device__ __forceinline__ bool candidate_accepted(const Dims& dims, const NzTable& tab, uint64_t seed,
+                                                   uint64_t pid, uint64_t iter, uint64_t j, uint32_t (&i)[D]) {
+    draw_index<D>(seed, pid, j, iter, kPurposeCandidate, dims.n, i);
+    return nz_find(tab, linear_key<D>(i, dims.n)) < 0;
+}
+
 // ---------------------------------------------------------------------------
 // Storage types.  bf16 is kept as raw 16-bit words; gathers widen to float.
 // ---------------------------------------------------------------------------

@@ -1,18 +1,39 @@
 // grad.hip -- model entries, weighted loss derivatives and the sparse MTTKRP
 // of the sampled GCP gradient (Kolda & Hong, Alg. 1-3 loop bodies and final
-// MTTKRP loop; eqs. Mdef, Y, mttkrp, Gks).
+// MTTKRP loop; eqs. Mdef, Y, mttkrp, Gks), plus the reduction of per-block
+// partial gradients, optionally fused with the Adam step (Alg. 4).
 //
-// Work mapping (wave64).  A wave owns a tile of 64 samples.  Phase A: lane l
-// produces sample (tile*64 + l) -- its Philox draw, data lookup and stratum --
-// so the counter-based generator runs once per sample.  Phase B: the wave
-// walks the tile in passes; in each pass a group of `lps` lanes (lps = the
-// power of two >= r) takes one sample, lane j of the group owns rank column
-// j.  The group gathers A_k(i_k, j) for every mode (one coalesced row read per
-// mode), forms the Hadamard product, reduces it over the group with xor
-// shuffles to get m_i, evaluates the weighted derivative, and scatters
-// ytilde * prod_{k' != k} A_k'(i_k', j) into every mode's FP64 accumulator.
-// Leave-one-out products come from prefix/suffix products, so no division.
+// Work mapping (wave64).  The sample set is cut into work items of 64
+// samples; persistent waves take items in turn.  Phase A: lane l produces
+// sample l of the item -- its Philox draw, data lookup and stratum -- so the
+// counter-based generator runs once per sample.  Phase B: the wave walks the
+// item in passes; in each pass a group of `lps` lanes (lps = the power of two
+// >= r) takes one sample and lane j of the group owns rank column j.  The
+// group gathers A_k(i_k, j) for every mode (one coalesced row read per mode),
+// forms the Hadamard product, reduces it over the group with xor shuffles to
+// get m_i, evaluates the weighted derivative, and scatters
+// ytilde * prod_{k' != k} A_k'(i_k', j) into every mode's gradient.  Leave-one-
+// out products come from prefix/suffix products, so no division.
+//
+// Scatter.  Device-scope atomics on MI355X sustain only ~170 G element-adds/s
+// (measured), far below what plain stores reach, so every mode whose rows fit
+// is accumulated privately per workgroup in LDS (FP64 ds_add), and each
+// workgroup writes its dense partial once with ordinary stores (rounded to
+// FP32).  A reduction kernel then sums the partials in FP64 in a fixed order
+// (deterministic).  Modes too long for LDS fall back to FP64 device atomics
+// into an accumulator that the call clears first.
+//
+// Stratified zeros.  The count kernel (sample.hip) has counted the accepted
+// candidates of every 64-candidate chunk and a scan has turned the counts
+// into exclusive prefixes.  A zero item here is one chunk: its wave redraws
+// the 64 candidates, ranks the accepted ones with a ballot, and keeps those
+// whose global rank is below q -- exactly the first q accepted in counter
+// order.  If the first batch held fewer than q zeros, the wave that owns the
+// last chunk keeps drawing candidates until q are found.
 #include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <unordered_set>
 
 #include "common.hpp"
 #include "device.hpp"
@@ -26,15 +47,25 @@ struct GradArgs {
     int format;
     int r;
     int lps;
-    int64_t S, p, nnz;
+    int64_t nnz;
     uint64_t seed, pid, iter;
     const void* values;
     const uint32_t* coo;
     NzTable tab;
-    const uint32_t* zero_list;  // stratified zeros, [q][D]
-    const uint32_t* idx;        // list mode: [S][D]
-    const void* ytilde;         // list mode: [S]
+    // direct items: samples c in [0, n_direct), 64 per item
+    int64_t n_direct, n_direct_items, p;
+    // stratified zeros: one item per chunk of 64 rejection candidates
+    int64_t n_zero_items, ncand, q;
+    const uint64_t* chunk_prefix;
+    // list mode (gcp_mttkrp): indices and ytilde per sample
+    const uint32_t* idx;
+    const void* ytilde;
     const void* A[GCP_MAX_D];
+    // scatter targets
+    uint32_t priv_mask;
+    int64_t lds_off[GCP_MAX_D];
+    int64_t lds_total;
+    void* partials;  // [gridDim.x][lds_total], FP64 for FP64 factors, else FP32
     double* acc;
     int64_t acc_off[GCP_MAX_D];
     double w[5];
@@ -42,18 +73,45 @@ struct GradArgs {
     double* loss_sum;
 };
 
+struct ReduceArgs {
+    int d;
+    int accumulate;
+    int64_t P;
+    int64_t off[GCP_MAX_D + 1];
+    uint32_t priv_mask;
+    int64_t lds_off[GCP_MAX_D];
+    int64_t lds_total;
+    int64_t nparts;
+    const void* partials;
+    const double* acc;
+    int64_t acc_off[GCP_MAX_D];
+    void* G[GCP_MAX_D];
+    // Adam (fused variant)
+    void* A;
+    float* A_master;
+    void* B;
+    void* C;
+    int64_t* state;
+    double alpha, beta1, beta2, eps, lower;
+    int eps_mode;
+};
+
+// Partial-gradient storage: FP64 for FP64 factors, FP32 otherwise.
+template <typename FT> struct Partial { using type = float; };
+template <> struct Partial<double> { using type = double; };
+
 template <typename T>
-__device__ __forceinline__ T pick_weight(const GradArgs& a, int code) {
+__device__ __forceinline__ T pick_weight(const double (&w)[5], int code) {
     // select chain: no dynamic indexing of the kernel-argument block
-    double w = a.w[0];
-    w = code == 1 ? a.w[1] : w;
-    w = code == 2 ? a.w[2] : w;
-    w = code == 3 ? a.w[3] : w;
-    w = code == 4 ? a.w[4] : w;
-    return (T)w;
+    double v = w[0];
+    v = code == 1 ? w[1] : v;
+    v = code == 2 ? w[2] : v;
+    v = code == 3 ? w[3] : v;
+    v = code == 4 ? w[4] : v;
+    return (T)v;
 }
 
-// Phase A: sample c's indices, data value and stratum (Alg. 1, 2, 3 draws).
+// Phase A for direct items: sample c's indices, data value and stratum.
 template <int D, typename VT, typename T>
 __device__ __forceinline__ void produce(const GradArgs& a, int64_t c, uint32_t (&i)[D], T& x, int& code) {
     const VT* __restrict__ vals = static_cast<const VT*>(a.values);
@@ -73,91 +131,140 @@ __device__ __forceinline__ void produce(const GradArgs& a, int64_t c, uint32_t (
         for (int k = 0; k < D; ++k) i[k] = a.coo[e * D + k];
         x = (T)vals[e];
         code = a.sampler == GCP_SAMPLER_SEMI_STRATIFIED ? GCP_STRATUM_NZ_CORR : GCP_STRATUM_NZ;
-    } else if (a.sampler == GCP_SAMPLER_SEMI_STRATIFIED) {
+    } else {
         draw_index<D>(a.seed, a.pid, (uint64_t)(c - a.p), a.iter, kPurposeUniform, a.dims.n, i);
         x = T(0);
         code = GCP_STRATUM_SEMI_ZERO;
-    } else {
-        const int64_t z = c - a.p;
-#pragma unroll
-        for (int k = 0; k < D; ++k) i[k] = a.zero_list[z * D + k];
-        x = T(0);
-        code = GCP_STRATUM_ZERO;
     }
 }
 
-template <int D, typename FT, typename VT, bool LIST>
-__global__ __launch_bounds__(256) void grad_kernel(GradArgs a) {
+// Phase B: the wave's 64 samples (one per lane in i/x/code/ylist) are
+// evaluated and scattered.  Every lane of the wave must call this.
+template <int D, typename FT, bool LIST>
+__device__ __forceinline__ void evaluate_and_scatter(const GradArgs& a, double* __restrict__ lds,
+                                                     const uint32_t (&i)[D],
+                                                     typename Compute<FT>::type x, int code,
+                                                     typename Compute<FT>::type ylist,
+                                                     typename Compute<FT>::type& fsum) {
     using T = typename Compute<FT>::type;
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
-    const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) / kWave;
     const int lps = a.lps;
     const int spw = kWave / lps;
     const int slot = lane / lps;
     const int j = lane & (lps - 1);
     const int r = a.r;
     const T eps = (T)a.eps;
+    for (int pass = 0; pass < lps; ++pass) {
+        const int src = pass * spw + slot;
+        uint32_t ii[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) ii[k] = __shfl(i[k], src);
+        const int cc = __shfl(code, src);
+        const bool live = cc >= 0;
+        const bool col = live && j < r;
+        T av[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+            av[k] = col ? widen(static_cast<const FT*>(a.A[k])[(size_t)ii[k] * r + j]) : T(0);
+        T pre[D], suf[D];
+        pre[0] = T(1);
+#pragma unroll
+        for (int k = 1; k < D; ++k) pre[k] = pre[k - 1] * av[k - 1];
+        suf[D - 1] = T(1);
+#pragma unroll
+        for (int k = D - 2; k >= 0; --k) suf[k] = suf[k + 1] * av[k + 1];
+        T y;
+        if constexpr (LIST) {
+            y = __shfl(ylist, src);
+        } else {
+            T m = pre[D - 1] * av[D - 1];
+            for (int o = lps >> 1; o > 0; o >>= 1) m += __shfl_xor(m, o);
+            const T xx = __shfl(x, src);
+            const T w = pick_weight<T>(a.w, cc);
+            T g = loss_g<T>(a.loss, xx, m, eps);
+            const bool corr = cc == GCP_STRATUM_NZ_CORR;
+            if (corr) g -= loss_g<T>(a.loss, T(0), m, eps);
+            y = w * g;
+            if (a.loss_sum && live && j == 0) {
+                T f = loss_f<T>(a.loss, xx, m, eps);
+                if (corr) f -= loss_f<T>(a.loss, T(0), m, eps);
+                fsum += w * f;
+            }
+        }
+        if (col) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const double v = (double)(y * pre[k] * suf[k]);
+                if ((a.priv_mask >> k) & 1u)
+                    atomicAdd(&lds[a.lds_off[k] + (int64_t)ii[k] * r + j], v);
+                else
+                    unsafeAtomicAdd(&a.acc[a.acc_off[k] + (int64_t)ii[k] * r + j], v);
+            }
+        }
+    }
+}
+
+// Exclusive prefix of a zero chunk.
+__device__ __forceinline__ uint64_t chunk_prefix(const GradArgs& a, int64_t chunk) {
+    return a.chunk_prefix[chunk];
+}
+
+template <int D, typename FT, typename VT, bool LIST>
+__global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
+    using T = typename Compute<FT>::type;
+    extern __shared__ double lds[];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nthreads = blockDim.x;
+    for (int64_t e = threadIdx.x; e < a.lds_total; e += nthreads) lds[e] = 0.0;
+    __syncthreads();
+
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    const int64_t n_items = a.n_direct_items + a.n_zero_items;
     T fsum = T(0);
 
-    for (int64_t tile = wave; tile * kWave < a.S; tile += nwave) {
-        const int64_t c = tile * kWave + lane;
+    for (int64_t item = wave; item < n_items; item += nwave) {
         uint32_t i[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) i[k] = 0;
         T x = T(0), ylist = T(0);
         int code = -1;
-        if (c < a.S) {
-            if constexpr (LIST) {
+        if (item < a.n_direct_items) {
+            const int64_t c = item * kWave + lane;
+            if (c < a.n_direct) {
+                if constexpr (LIST) {
 #pragma unroll
-                for (int k = 0; k < D; ++k) i[k] = a.idx[c * D + k];
-                ylist = static_cast<const T*>(a.ytilde)[c];
-                code = 0;
-            } else {
-                produce<D, VT, T>(a, c, i, x, code);
-            }
-        }
-        for (int pass = 0; pass < lps; ++pass) {
-            const int src = pass * spw + slot;
-            uint32_t ii[D];
-#pragma unroll
-            for (int k = 0; k < D; ++k) ii[k] = __shfl(i[k], src);
-            const int cc = __shfl(code, src);
-            const bool live = cc >= 0;
-            const bool col = live && j < r;
-            T av[D];
-#pragma unroll
-            for (int k = 0; k < D; ++k)
-                av[k] = col ? widen(static_cast<const FT*>(a.A[k])[(size_t)ii[k] * r + j]) : T(0);
-            T pre[D], suf[D];
-            pre[0] = T(1);
-#pragma unroll
-            for (int k = 1; k < D; ++k) pre[k] = pre[k - 1] * av[k - 1];
-            suf[D - 1] = T(1);
-#pragma unroll
-            for (int k = D - 2; k >= 0; --k) suf[k] = suf[k + 1] * av[k + 1];
-            T y;
-            if constexpr (LIST) {
-                y = __shfl(ylist, src);
-            } else {
-                T m = pre[D - 1] * av[D - 1];
-                for (int o = lps >> 1; o > 0; o >>= 1) m += __shfl_xor(m, o);
-                const T xx = __shfl(x, src);
-                const T w = pick_weight<T>(a, cc);
-                T g = loss_g<T>(a.loss, xx, m, eps);
-                const bool corr = cc == GCP_STRATUM_NZ_CORR;
-                if (corr) g -= loss_g<T>(a.loss, T(0), m, eps);
-                y = w * g;
-                if (a.loss_sum && live && j == 0) {
-                    T f = loss_f<T>(a.loss, xx, m, eps);
-                    if (corr) f -= loss_f<T>(a.loss, T(0), m, eps);
-                    fsum += w * f;
+                    for (int k = 0; k < D; ++k) i[k] = a.idx[c * D + k];
+                    ylist = static_cast<const T*>(a.ytilde)[c];
+                    code = 0;
+                } else {
+                    produce<D, VT, T>(a, c, i, x, code);
                 }
             }
-            if (col) {
-#pragma unroll
-                for (int k = 0; k < D; ++k)
-                    unsafeAtomicAdd(&a.acc[a.acc_off[k] + (int64_t)ii[k] * r + j], (double)(y * pre[k] * suf[k]));
+            evaluate_and_scatter<D, FT, LIST>(a, lds, i, x, code, ylist, fsum);
+        } else if constexpr (!LIST) {
+            // stratified zeros: one chunk of 64 rejection candidates
+            const int64_t chunk = item - a.n_direct_items;
+            const uint64_t j = (uint64_t)chunk * kWave + lane;
+            const bool acc = j < (uint64_t)a.ncand && candidate_accepted<D>(a.dims, a.tab, a.seed, a.pid, a.iter, j, i);
+            const uint64_t bal = __ballot(acc);
+            const uint64_t rank = chunk_prefix(a, chunk) + __popcll(bal & ((1ull << lane) - 1ull));
+            code = (acc && rank < (uint64_t)a.q) ? GCP_STRATUM_ZERO : -1;
+            evaluate_and_scatter<D, FT, false>(a, lds, i, x, code, ylist, fsum);
+            if (chunk == a.n_zero_items - 1) {
+                // first batch short of q zeros: continue the counter stream (wave-uniform loop)
+                uint64_t filled = a.chunk_prefix[a.n_zero_items];
+                uint64_t base = (uint64_t)a.ncand;
+                for (int64_t t = 0; t < kRejMaxRefillTiles * 16 && filled < (uint64_t)a.q; ++t) {
+                    const uint64_t jj = base + lane;
+                    const bool ok = candidate_accepted<D>(a.dims, a.tab, a.seed, a.pid, a.iter, jj, i);
+                    const uint64_t b2 = __ballot(ok);
+                    const uint64_t rk = filled + __popcll(b2 & ((1ull << lane) - 1ull));
+                    const int cz = (ok && rk < (uint64_t)a.q) ? GCP_STRATUM_ZERO : -1;
+                    evaluate_and_scatter<D, FT, false>(a, lds, i, x, cz, ylist, fsum);
+                    filled += __popcll(b2);
+                    base += kWave;
+                }
             }
         }
     }
@@ -168,6 +275,11 @@ __global__ __launch_bounds__(256) void grad_kernel(GradArgs a) {
             if (lane == 0 && f != 0.0) unsafeAtomicAdd(a.loss_sum, f);
         }
     }
+    __syncthreads();
+    // one dense partial per workgroup, plain stores (FP32 unless the factors are FP64)
+    using PT = typename Partial<FT>::type;
+    PT* __restrict__ part = static_cast<PT*>(a.partials) + (int64_t)blockIdx.x * a.lds_total;
+    for (int64_t e = threadIdx.x; e < a.lds_total; e += nthreads) part[e] = (PT)lds[e];
 }
 
 // ---------------------------------------------------------------------------
@@ -207,12 +319,7 @@ __global__ __launch_bounds__(256) void loss_grad_kernel(LossArgs a) {
             m += prod;
         }
         const int code = a.stratum[c];
-        double wd = a.w[0];
-        wd = code == 1 ? a.w[1] : wd;
-        wd = code == 2 ? a.w[2] : wd;
-        wd = code == 3 ? a.w[3] : wd;
-        wd = code == 4 ? a.w[4] : wd;
-        const T w = (T)wd;
+        const T w = pick_weight<T>(a.w, code);
         const T x = (T) static_cast<const VT*>(a.xval)[c];
         const bool corr = code == GCP_STRATUM_NZ_CORR;
         T g = loss_g<T>(a.loss, x, m, eps);
@@ -231,45 +338,111 @@ __global__ __launch_bounds__(256) void loss_grad_kernel(LossArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Accumulator clear and final rounding into G.
+// Reduction: G = sum of the per-workgroup partials (fixed order, FP64) for
+// privatised modes, the FP64 accumulator for the others; optionally the Adam
+// step on the same elements.  Elements are numbered over all modes in mode
+// order (the flat parameter layout), 64 per workgroup; the 16 waves of a
+// workgroup each sum every 16th partial and the wave sums are combined in
+// wave order.
 // ---------------------------------------------------------------------------
+constexpr int kRedWaves = 16;
+
+template <typename GT, int ADAM>
+__global__ __launch_bounds__(kRedWaves * kWave) void reduce_kernel(ReduceArgs a) {
+    __shared__ double wave_sum[kRedWaves][kWave];
+    __shared__ int64_t t_shared;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    const int64_t e = (int64_t)blockIdx.x * kWave + lane;
+    const bool in = e < a.P;
+    int k = 0;
+#pragma unroll
+    for (int t = 1; t < GCP_MAX_D; ++t)
+        if (t < a.d && e >= a.off[t]) k = t;
+    const int64_t local = in ? e - a.off[k] : 0;
+    const bool priv = (a.priv_mask >> k) & 1u;
+    double s = 0.0;
+    if (in && priv) {
+        const int64_t pe = a.lds_off[k] + local;
+        const GT* __restrict__ parts = static_cast<const GT*>(a.partials);  // partial type = gradient type
+        for (int64_t b = wv; b < a.nparts; b += kRedWaves) s += (double)parts[b * a.lds_total + pe];
+    }
+    wave_sum[wv][lane] = s;
+    if (ADAM && threadIdx.x == 0) t_shared = a.state[0] + 1;
+    __syncthreads();
+    if (wv == 0) {
+        double g = 0.0;
+        if (priv) {
+#pragma unroll
+            for (int w = 0; w < kRedWaves; ++w) g += wave_sum[w][lane];
+        } else if (in) {
+            g = a.acc[a.acc_off[k] + local];
+        }
+        if (in) {
+            void* gk = a.G[0];
+#pragma unroll
+            for (int t = 1; t < GCP_MAX_D; ++t)
+                if (t == k) gk = a.G[t];
+            if (gk) {
+                GT* Gp = static_cast<GT*>(gk);
+                double v = g;
+                if (a.accumulate) v += (double)Gp[local];
+                Gp[local] = (GT)v;
+            }
+        }
+        if constexpr (ADAM != 0) {
+            if (in) {
+                using T = GT;  // moment type: double for F64 factors, float otherwise
+                const int64_t t = t_shared;
+                const T gt = (T)g;
+                const T b1 = (T)a.beta1, b2 = (T)a.beta2;
+                const T omb1 = (T)(1.0 - a.beta1), omb2 = (T)(1.0 - a.beta2);
+                const T bc1 = (T)(1.0 - pow(a.beta1, (double)t));
+                const T bc2 = (T)(1.0 - pow(a.beta2, (double)t));
+                T* B = static_cast<T*>(a.B);
+                T* C = static_cast<T*>(a.C);
+                const T bm = b1 * B[e] + omb1 * gt;
+                const T cm = b2 * C[e] + omb2 * gt * gt;
+                B[e] = bm;
+                C[e] = cm;
+                const T bhat = bm / bc1, chat = cm / bc2;
+                const T den = a.eps_mode == GCP_EPS_INSIDE_SQRT ? sqrt(chat + (T)a.eps) : sqrt(chat) + (T)a.eps;
+                const T step = (T)a.alpha * bhat / den;
+                if constexpr (ADAM == 2) {
+                    float v = a.A_master[e] - (float)step;
+                    v = v < (float)a.lower ? (float)a.lower : v;
+                    a.A_master[e] = v;
+                    static_cast<bf16_t*>(a.A)[e] = to_bf16(v);
+                } else {
+                    T* A = static_cast<T*>(a.A);
+                    T v = A[e] - step;
+                    A[e] = v < (T)a.lower ? (T)a.lower : v;
+                }
+            }
+        }
+    }
+    if constexpr (ADAM != 0) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();
+            const unsigned long long done =
+                atomicAdd(reinterpret_cast<unsigned long long*>(&a.state[1]), 1ull);
+            if (done == (unsigned long long)gridDim.x - 1ull) {
+                a.state[0] = t_shared;
+                a.state[1] = 0;
+            }
+        }
+    }
+}
+
 __global__ void fill_zero_kernel(double* __restrict__ p, int64_t n) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
          e += (int64_t)gridDim.x * blockDim.x)
         p[e] = 0.0;
 }
 
-struct FinArgs {
-    int d;
-    int accumulate;
-    int64_t off[GCP_MAX_D + 1];
-    void* G[GCP_MAX_D];
-    const double* acc;
-};
-
-template <typename GT>
-__global__ void finalize_kernel(FinArgs a) {
-    const int64_t total = a.off[a.d];
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        int k = 0;
-#pragma unroll
-        for (int t = 1; t < GCP_MAX_D; ++t)
-            if (t < a.d && e >= a.off[t]) k = t;
-        void* gk = a.G[0];
-#pragma unroll
-        for (int t = 1; t < GCP_MAX_D; ++t)
-            if (t == k) gk = a.G[t];
-        GT* G = static_cast<GT*>(gk);
-        const int64_t local = e - a.off[k];
-        double v = a.acc[e];
-        if (a.accumulate) v += (double)G[local];
-        G[local] = (GT)v;
-    }
-}
-
 // ---------------------------------------------------------------------------
-// Host launchers
+// Host side
 // ---------------------------------------------------------------------------
 static int grid_cap(int64_t n, int threads, int cap) {
     int64_t b = (n + threads - 1) / threads;
@@ -278,21 +451,19 @@ static int grid_cap(int64_t n, int threads, int cap) {
     return (int)b;
 }
 
+// Lets a kernel take up to 160 KB of dynamic LDS (set once per kernel).
+static void allow_full_lds(const void* kernel) {
+    static std::mutex mu;
+    static std::unordered_set<const void*> done;
+    std::lock_guard<std::mutex> lk(mu);
+    if (done.insert(kernel).second)
+        (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
 static int lanes_per_sample(int64_t r) {
     int l = 1;
     while (l < r) l <<= 1;
     return l;
-}
-
-AccLayout acc_layout(const gcp_tensor* X, const gcp_factors* M) {
-    AccLayout L{};
-    int64_t off = 0;
-    for (int k = 0; k < X->d; ++k) {
-        L.offset[k] = off;
-        off += X->dims[k] * M->rank;
-    }
-    for (int k = X->d; k <= GCP_MAX_D; ++k) L.offset[k] = off;
-    return L;
 }
 
 gcp_status launch_fill_zero(double* p, int64_t n, hipStream_t s) {
@@ -301,39 +472,88 @@ gcp_status launch_fill_zero(double* p, int64_t n, hipStream_t s) {
     return check_launch("accumulator clear");
 }
 
-gcp_status launch_finalize(const gcp_tensor* X, const gcp_factors* M, const double* acc, const AccLayout& L,
-                           void* const* G, int accumulate, hipStream_t s) {
-    FinArgs a{};
-    a.d = X->d;
-    a.accumulate = accumulate;
-    for (int k = 0; k <= GCP_MAX_D; ++k) a.off[k] = L.offset[k];
-    for (int k = 0; k < X->d; ++k) a.G[k] = G[k];
-    a.acc = acc;
-    const int64_t n = L.offset[X->d];
-    if (n <= 0) return GCP_OK;
-    const dim3 g(grid_cap(n, 256, 4096)), b(256);
-    if (M->dtype == GCP_F64) hipLaunchKernelGGL(finalize_kernel<double>, g, b, 0, s, a);
-    else hipLaunchKernelGGL(finalize_kernel<float>, g, b, 0, s, a);
-    return check_launch("gradient rounding");
+ScatterPlan plan_scatter(const gcp_tensor* X, const gcp_factors* M, int64_t n_items) {
+    ScatterPlan pl{};
+    pl.d = X->d;
+    const int64_t r = M->rank;
+    // flat element offsets (mode order)
+    int64_t off = 0;
+    for (int k = 0; k < X->d; ++k) {
+        pl.off[k] = off;
+        off += X->dims[k] * r;
+    }
+    for (int k = X->d; k <= GCP_MAX_D; ++k) pl.off[k] = off;
+    pl.P = off;
+    // privatise the shortest modes first while their FP64 partials fit in LDS
+    int order[GCP_MAX_D];
+    for (int k = 0; k < X->d; ++k) order[k] = k;
+    for (int a = 0; a < X->d; ++a)
+        for (int b = a + 1; b < X->d; ++b)
+            if (X->dims[order[b]] < X->dims[order[a]]) {
+                const int t = order[a];
+                order[a] = order[b];
+                order[b] = t;
+            }
+    const int64_t budget = kLdsBudgetBytes / 8;
+    int64_t lds = 0, acc = 0;
+    for (int a = 0; a < X->d; ++a) {
+        const int k = order[a];
+        const int64_t n = X->dims[k] * r;
+        if (lds + n <= budget) {
+            pl.priv_mask |= 1u << k;
+            pl.lds_off[k] = lds;
+            lds += n;
+        }
+    }
+    for (int k = 0; k < X->d; ++k)
+        if (!((pl.priv_mask >> k) & 1u)) {
+            pl.acc_off[k] = acc;
+            acc += X->dims[k] * r;
+        }
+    pl.lds_total = lds;
+    pl.acc_total = acc;
+    // launch shape: big LDS footprints get one 1024-thread workgroup per CU
+    const int64_t lds_bytes = lds * 8;
+    pl.threads = lds_bytes > 40 * 1024 ? 1024 : 512;
+    int per_cu = lds_bytes > 0 ? (int)((160 * 1024) / (lds_bytes + 1024)) : 4;
+    const int max_per_cu = 2048 / pl.threads;
+    if (per_cu > max_per_cu) per_cu = max_per_cu;
+    if (per_cu < 1) per_cu = 1;
+    const int64_t waves_per_block = pl.threads / kWave;
+    int64_t blocks = (int64_t)device_cu_count() * per_cu;
+    const int64_t need = (n_items + waves_per_block - 1) / waves_per_block;
+    if (blocks > need) blocks = need;
+    if (blocks < 1) blocks = 1;
+    pl.blocks = blocks;
+    return pl;
+}
+
+size_t scatter_partials_bytes(const ScatterPlan& pl, int fdtype) {
+    return (size_t)(pl.blocks * pl.lds_total) * (fdtype == GCP_F64 ? 8u : 4u);
 }
 
 template <int D, bool LIST>
-static void grad_launch(const GradArgs& a, int fdtype, int vdtype, hipStream_t s) {
-    const int64_t tiles = (a.S + kWave - 1) / kWave;
-    const dim3 g(grid_cap(tiles * kWave, 256, 4096)), b(256);
+static void grad_launch(const GradArgs& a, const ScatterPlan& pl, int fdtype, int vdtype, hipStream_t s) {
+    const dim3 g((unsigned)pl.blocks), b((unsigned)pl.threads);
+    const size_t shm = (size_t)pl.lds_total * 8;
+    auto go = [&](auto kernel) {
+        allow_full_lds(reinterpret_cast<const void*>(kernel));
+        hipLaunchKernelGGL(kernel, g, b, shm, s, a);
+    };
     if (fdtype == GCP_F64) {
-        if (vdtype == GCP_F64) hipLaunchKernelGGL((grad_kernel<D, double, double, LIST>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((grad_kernel<D, double, float, LIST>), g, b, 0, s, a);
+        if (vdtype == GCP_F64) go(grad_kernel<D, double, double, LIST>);
+        else go(grad_kernel<D, double, float, LIST>);
     } else if (fdtype == GCP_F32) {
-        if (vdtype == GCP_F64) hipLaunchKernelGGL((grad_kernel<D, float, double, LIST>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((grad_kernel<D, float, float, LIST>), g, b, 0, s, a);
+        if (vdtype == GCP_F64) go(grad_kernel<D, float, double, LIST>);
+        else go(grad_kernel<D, float, float, LIST>);
     } else {
-        if (vdtype == GCP_F64) hipLaunchKernelGGL((grad_kernel<D, bf16_t, double, LIST>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((grad_kernel<D, bf16_t, float, LIST>), g, b, 0, s, a);
+        if (vdtype == GCP_F64) go(grad_kernel<D, bf16_t, double, LIST>);
+        else go(grad_kernel<D, bf16_t, float, LIST>);
     }
 }
 
-static GradArgs base_args(const gcp_tensor* X, const gcp_factors* M, double* acc, const AccLayout& L) {
+static GradArgs base_args(const gcp_tensor* X, const gcp_factors* M, const ScatterPlan& pl, double* acc,
+                          void* partials) {
     GradArgs a{};
     for (int k = 0; k < X->d; ++k) a.dims.n[k] = X->dims[k];
     a.format = X->format;
@@ -349,41 +569,110 @@ static GradArgs base_args(const gcp_tensor* X, const gcp_factors* M, double* acc
     }
     for (int k = 0; k < X->d; ++k) {
         a.A[k] = M->A[k];
-        a.acc_off[k] = L.offset[k];
+        a.lds_off[k] = pl.lds_off[k];
+        a.acc_off[k] = pl.acc_off[k];
     }
+    a.priv_mask = pl.priv_mask;
+    a.lds_total = pl.lds_total;
     a.acc = acc;
+    a.partials = partials;
     return a;
 }
 
-gcp_status launch_mttkrp_list(const gcp_tensor* X, const gcp_factors* M, const uint32_t* idx, const void* ytilde,
-                              int64_t S, double* acc, const AccLayout& L, hipStream_t s) {
-    if (S <= 0) return GCP_OK;
-    GradArgs a = base_args(X, M, acc, L);
-    a.S = S;
+gcp_status launch_grad_list(const gcp_tensor* X, const gcp_factors* M, const uint32_t* idx, const void* ytilde,
+                            int64_t S, const ScatterPlan& pl, double* acc, void* partials, hipStream_t s) {
+    GradArgs a = base_args(X, M, pl, acc, partials);
+    a.n_direct = S;
+    a.n_direct_items = (S + kWave - 1) / kWave;
     a.idx = idx;
     a.ytilde = ytilde;
-    dispatch_d(X->d, [&](auto dc) { grad_launch<decltype(dc)::value, true>(a, M->dtype, GCP_F32, s); });
+    dispatch_d(X->d, [&](auto dc) { grad_launch<decltype(dc)::value, true>(a, pl, M->dtype, GCP_F32, s); });
     return check_launch("gcp_mttkrp");
 }
 
-gcp_status launch_fused(gcp_loss loss, const gcp_tensor* X, const gcp_factors* M, const gcp_sampling* cfg,
-                        double eps, const uint32_t* zero_list, double* acc, const AccLayout& L,
-                        double* loss_sum, hipStream_t s) {
-    GradArgs a = base_args(X, M, acc, L);
+int64_t fused_items(const gcp_sampling* cfg, int64_t ncand) {
+    if (cfg->sampler == GCP_SAMPLER_UNIFORM) return (cfg->s + kWave - 1) / kWave;
+    if (cfg->sampler == GCP_SAMPLER_SEMI_STRATIFIED) return (cfg->p + cfg->q + kWave - 1) / kWave;
+    const int64_t zero_items = cfg->q > 0 ? (ncand + kWave - 1) / kWave : 0;
+    return (cfg->p + kWave - 1) / kWave + zero_items;
+}
+
+gcp_status launch_grad_fused(gcp_loss loss, const gcp_tensor* X, const gcp_factors* M, const gcp_sampling* cfg,
+                             double eps, const ScatterPlan& pl, int64_t ncand, const uint64_t* chunk_prefix,
+                             double* acc, void* partials, double* loss_sum, hipStream_t s) {
+    GradArgs a = base_args(X, M, pl, acc, partials);
     a.loss = loss;
     a.sampler = cfg->sampler;
-    a.S = cfg->sampler == GCP_SAMPLER_UNIFORM ? cfg->s : cfg->p + cfg->q;
-    a.p = cfg->sampler == GCP_SAMPLER_UNIFORM ? 0 : cfg->p;
     a.seed = cfg->seed;
     a.pid = cfg->problem_id;
     a.iter = cfg->iteration;
-    a.zero_list = zero_list;
     stratum_weights(X, cfg, a.w);
     a.eps = eps;
     a.loss_sum = loss_sum;
-    if (a.S <= 0) return GCP_OK;
-    dispatch_d(X->d, [&](auto dc) { grad_launch<decltype(dc)::value, false>(a, M->dtype, X->vdtype, s); });
+    if (cfg->sampler == GCP_SAMPLER_UNIFORM) {
+        a.n_direct = cfg->s;
+        a.p = 0;
+    } else if (cfg->sampler == GCP_SAMPLER_SEMI_STRATIFIED) {
+        a.n_direct = cfg->p + cfg->q;
+        a.p = cfg->p;
+    } else {
+        a.n_direct = cfg->p;
+        a.p = cfg->p;
+        a.q = cfg->q;
+        a.ncand = ncand;
+        a.chunk_prefix = chunk_prefix;
+        a.n_zero_items = cfg->q > 0 ? (ncand + kWave - 1) / kWave : 0;
+    }
+    a.n_direct_items = (a.n_direct + kWave - 1) / kWave;
+    // with nothing sampled the single workgroup still publishes a zero partial
+    dispatch_d(X->d, [&](auto dc) { grad_launch<decltype(dc)::value, false>(a, pl, M->dtype, X->vdtype, s); });
     return check_launch("gcp_sampled_grad");
+}
+
+gcp_status launch_reduce(const gcp_factors* M, const ScatterPlan& pl, const double* acc, const void* partials,
+                         void* const* G, int accumulate, const AdamParams* adam, hipStream_t s) {
+    ReduceArgs a{};
+    a.d = pl.d;
+    a.P = pl.P;
+    for (int k = 0; k <= GCP_MAX_D; ++k) a.off[k] = pl.off[k];
+    for (int k = 0; k < pl.d; ++k) {
+        a.lds_off[k] = pl.lds_off[k];
+        a.acc_off[k] = pl.acc_off[k];
+        a.G[k] = G ? G[k] : nullptr;
+    }
+    a.priv_mask = pl.priv_mask;
+    a.lds_total = pl.lds_total;
+    a.nparts = pl.blocks;
+    a.partials = partials;
+    a.acc = acc;
+    a.accumulate = accumulate;
+    if (adam) {
+        a.A = adam->A;
+        a.A_master = adam->A_master;
+        a.B = adam->B;
+        a.C = adam->C;
+        a.state = adam->state;
+        a.alpha = adam->alpha;
+        a.beta1 = adam->beta1;
+        a.beta2 = adam->beta2;
+        a.eps = adam->eps;
+        a.lower = adam->lower;
+        a.eps_mode = adam->eps_mode;
+    }
+    if (pl.P <= 0) return GCP_OK;
+    const dim3 g((unsigned)((pl.P + kWave - 1) / kWave)), b(kRedWaves * kWave);
+    const bool f64 = M->dtype == GCP_F64;
+    if (!adam) {
+        if (f64) hipLaunchKernelGGL((reduce_kernel<double, 0>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((reduce_kernel<float, 0>), g, b, 0, s, a);
+    } else if (f64) {
+        hipLaunchKernelGGL((reduce_kernel<double, 1>), g, b, 0, s, a);
+    } else if (M->dtype == GCP_F32) {
+        hipLaunchKernelGGL((reduce_kernel<float, 1>), g, b, 0, s, a);
+    } else {
+        hipLaunchKernelGGL((reduce_kernel<float, 2>), g, b, 0, s, a);
+    }
+    return check_launch("gradient reduction");
 }
 
 template <int D>

@@ -104,9 +104,9 @@ __global__ void sample_direct_kernel(DirectArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Rejection pipeline for stratified zeros.
-// Candidate j of tile b is j = b * 1024 + item * 256 + tid (item-major), so a
-// wave ballot per item ranks accepted candidates in counter order.
+// Rejection pipeline for stratified zeros.  Candidate j belongs to chunk
+// j / 64; one wave examines one chunk, so a ballot ranks its accepted
+// candidates in counter order.
 // ---------------------------------------------------------------------------
 struct RejArgs {
     Dims dims;
@@ -119,67 +119,48 @@ struct RejArgs {
     void* xval;
     uint8_t* stratum;
     int vdtype;
-    uint32_t* block_count;
-    uint64_t* block_offset;
-    uint64_t* total;
+    uint32_t* chunk_count;
+    uint64_t* chunk_prefix;
     uint32_t* status;
+    int64_t nchunks;
 };
 
 template <int D>
-__device__ __forceinline__ bool candidate_accepted(const RejArgs& a, uint64_t j, uint32_t (&i)[D]) {
-    draw_index<D>(a.seed, a.pid, j, a.iter, kPurposeCandidate, a.dims.n, i);
-    return nz_find(a.tab, linear_key<D>(i, a.dims.n)) < 0;
-}
-
-template <int D>
 __global__ __launch_bounds__(kRejThreads) void rej_count_kernel(RejArgs a) {
-    __shared__ uint32_t wave_cnt[kRejThreads / kWave];
-    const int tid = threadIdx.x;
-    const uint64_t base = (uint64_t)blockIdx.x * kRejTile;
-    uint32_t mine = 0;
-#pragma unroll
-    for (int it = 0; it < kRejItems; ++it) {
-        const uint64_t j = base + (uint64_t)it * kRejThreads + tid;
-        uint32_t i[D];
-        if (j < (uint64_t)a.ncand && candidate_accepted<D>(a, j, i)) ++mine;
-    }
-    // wave sum then block sum
-    for (int o = kWave / 2; o > 0; o >>= 1) mine += __shfl_xor(mine, o);
-    if ((tid & (kWave - 1)) == 0) wave_cnt[tid / kWave] = mine;
-    __syncthreads();
-    if (tid == 0) {
-        uint32_t t = 0;
-        for (int w = 0; w < kRejThreads / kWave; ++w) t += wave_cnt[w];
-        a.block_count[blockIdx.x] = t;
-    }
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    uint32_t i[D];
+    const bool acc = j < a.ncand && candidate_accepted<D>(a.dims, a.tab, a.seed, a.pid, a.iter, (uint64_t)j, i);
+    const uint64_t bal = __ballot(acc);
+    const int64_t chunk = j / kRejChunk;
+    if ((threadIdx.x & (kWave - 1)) == 0 && chunk < a.nchunks) a.chunk_count[chunk] = (uint32_t)__popcll(bal);
 }
 
-// Exclusive scan of the per-tile counts by one workgroup of 1024 threads.
-__global__ __launch_bounds__(1024) void rej_scan_kernel(RejArgs a, int64_t nblk) {
+// Exclusive scan of the chunk counts by one workgroup of 1024 threads;
+// chunk_prefix[nchunks] receives the total.
+__global__ __launch_bounds__(1024) void rej_scan_kernel(RejArgs a) {
     __shared__ uint64_t part[1024];
     __shared__ uint64_t carry;
     const int tid = threadIdx.x;
     if (tid == 0) carry = 0;
     __syncthreads();
-    for (int64_t base = 0; base < nblk; base += 1024) {
+    for (int64_t base = 0; base < a.nchunks; base += 1024) {
         const int64_t b = base + tid;
-        const uint64_t v = b < nblk ? a.block_count[b] : 0;
+        const uint64_t v = b < a.nchunks ? a.chunk_count[b] : 0;
         part[tid] = v;
         __syncthreads();
-        // Hillis-Steele inclusive scan in LDS
-        for (int o = 1; o < 1024; o <<= 1) {
+        for (int o = 1; o < 1024; o <<= 1) {  // Hillis-Steele inclusive scan
             const uint64_t add = tid >= o ? part[tid - o] : 0;
             __syncthreads();
             part[tid] += add;
             __syncthreads();
         }
-        if (b < nblk) a.block_offset[b] = carry + part[tid] - v;
+        if (b < a.nchunks) a.chunk_prefix[b] = carry + part[tid] - v;
         __syncthreads();
         if (tid == 1023) carry += part[1023];
         __syncthreads();
     }
     if (tid == 0) {
-        a.total[0] = carry;
+        a.chunk_prefix[a.nchunks] = carry;
         a.status[0] = 0;
     }
 }
@@ -196,57 +177,37 @@ __device__ __forceinline__ void write_zero(const RejArgs& a, uint64_t rank, cons
     if (a.stratum) a.stratum[o] = GCP_STRATUM_ZERO;
 }
 
-// Block-wide exclusive ranks of accepted flags, in item-major candidate order.
-template <int D>
-__device__ __forceinline__ uint64_t rank_and_write(const RejArgs& a, uint64_t tile_first_rank,
-                                                   uint64_t base, uint64_t limit,
-                                                   uint32_t* wave_cnt) {
-    const int tid = threadIdx.x;
-    const int lane = tid & (kWave - 1);
-    const int wave = tid / kWave;
-    uint64_t running = tile_first_rank;
-    for (int it = 0; it < kRejItems; ++it) {
-        const uint64_t j = base + (uint64_t)it * kRejThreads + tid;
-        uint32_t i[D];
-        const bool acc = j < limit && candidate_accepted<D>(a, j, i);
-        const uint64_t bal = __ballot(acc);
-        const uint32_t before = __popcll(bal & ((1ull << lane) - 1ull));
-        if (lane == 0) wave_cnt[wave] = __popcll(bal);
-        __syncthreads();
-        uint64_t wave_base = 0, item_total = 0;
-        for (int w = 0; w < kRejThreads / kWave; ++w) {
-            if (w < wave) wave_base += wave_cnt[w];
-            item_total += wave_cnt[w];
-        }
-        const uint64_t rank = running + wave_base + before;
-        if (acc && rank < (uint64_t)a.q) write_zero<D>(a, rank, i);
-        running += item_total;
-        __syncthreads();
-    }
-    return running;
-}
-
 template <int D>
 __global__ __launch_bounds__(kRejThreads) void rej_write_kernel(RejArgs a) {
-    __shared__ uint32_t wave_cnt[kRejThreads / kWave];
-    const uint64_t first = a.block_offset[blockIdx.x];
-    if (first >= (uint64_t)a.q) return;  // block-uniform exit
-    rank_and_write<D>(a, first, (uint64_t)blockIdx.x * kRejTile, (uint64_t)a.ncand, wave_cnt);
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
+    uint32_t i[D];
+    const bool acc = j < a.ncand && candidate_accepted<D>(a.dims, a.tab, a.seed, a.pid, a.iter, (uint64_t)j, i);
+    const uint64_t bal = __ballot(acc);
+    const int64_t chunk = j / kRejChunk;
+    if (chunk >= a.nchunks) return;  // whole wave beyond the batch
+    const uint64_t rank = a.chunk_prefix[chunk] + __popcll(bal & ((1ull << lane) - 1ull));
+    if (acc && rank < (uint64_t)a.q) write_zero<D>(a, rank, i);
 }
 
 // Continues the candidate stream after the first batch until q zeros exist.
-// Every thread of the single workgroup sees the same `filled` and exits together.
+// One wave; `filled` is wave-uniform, so all lanes leave the loop together.
 template <int D>
-__global__ __launch_bounds__(kRejThreads) void rej_refill_kernel(RejArgs a) {
-    __shared__ uint32_t wave_cnt[kRejThreads / kWave];
-    uint64_t filled = a.total[0];
+__global__ __launch_bounds__(kWave) void rej_refill_kernel(RejArgs a) {
+    const int lane = threadIdx.x;
+    uint64_t filled = a.chunk_prefix[a.nchunks];
     if (filled >= (uint64_t)a.q) return;
     uint64_t base = (uint64_t)a.ncand;
-    for (int64_t t = 0; t < kRejMaxRefillTiles && filled < (uint64_t)a.q; ++t) {
-        filled = rank_and_write<D>(a, filled, base, ~0ull, wave_cnt);
-        base += kRejTile;
+    for (int64_t t = 0; t < kRejMaxRefillTiles * 16 && filled < (uint64_t)a.q; ++t) {
+        uint32_t i[D];
+        const bool acc = candidate_accepted<D>(a.dims, a.tab, a.seed, a.pid, a.iter, base + lane, i);
+        const uint64_t bal = __ballot(acc);
+        const uint64_t rank = filled + __popcll(bal & ((1ull << lane) - 1ull));
+        if (acc && rank < (uint64_t)a.q) write_zero<D>(a, rank, i);
+        filled += __popcll(bal);
+        base += kWave;
     }
-    if (threadIdx.x == 0 && filled < (uint64_t)a.q) a.status[0] = 1;
+    if (lane == 0 && filled < (uint64_t)a.q) a.status[0] = 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -325,18 +286,7 @@ gcp_status launch_sample_direct(const gcp_tensor* X, const gcp_sampling* cfg, in
     return check_launch("gcp_sample");
 }
 
-template <int D>
-static void rejection_launch(const RejArgs& a, int64_t nblk, hipStream_t s) {
-    hipLaunchKernelGGL(rej_count_kernel<D>, dim3((unsigned)nblk), dim3(kRejThreads), 0, s, a);
-    hipLaunchKernelGGL(rej_scan_kernel, dim3(1), dim3(1024), 0, s, a, nblk);
-    hipLaunchKernelGGL(rej_write_kernel<D>, dim3((unsigned)nblk), dim3(kRejThreads), 0, s, a);
-    hipLaunchKernelGGL(rej_refill_kernel<D>, dim3(1), dim3(kRejThreads), 0, s, a);
-}
-
-gcp_status launch_rejection(const gcp_tensor* X, const gcp_sampling* cfg, int64_t ncand,
-                            const RejScratch& rs, uint32_t* idx_out, int64_t p_off, void* xval,
-                            uint8_t* stratum, hipStream_t s) {
-    if (cfg->q <= 0) return GCP_OK;
+static RejArgs rej_args(const gcp_tensor* X, const gcp_sampling* cfg, int64_t ncand, const RejScratch& rs) {
     RejArgs a{};
     a.dims = make_dims(X);
     a.seed = cfg->seed;
@@ -344,18 +294,44 @@ gcp_status launch_rejection(const gcp_tensor* X, const gcp_sampling* cfg, int64_
     a.iter = cfg->iteration;
     a.ncand = ncand;
     a.q = cfg->q;
-    a.p_off = p_off;
     a.tab = make_table(X->nz_table, X->nz_slots);
+    a.vdtype = X->vdtype;
+    a.chunk_count = rs.chunk_count;
+    a.chunk_prefix = rs.chunk_prefix;
+    a.status = rs.status;
+    a.nchunks = rs.nchunks;
+    return a;
+}
+
+gcp_status launch_rejection_count(const gcp_tensor* X, const gcp_sampling* cfg, int64_t ncand,
+                                  const RejScratch& rs, hipStream_t s) {
+    if (cfg->q <= 0) return GCP_OK;
+    const RejArgs a = rej_args(X, cfg, ncand, rs);
+    const unsigned blocks = (unsigned)((ncand + kRejThreads - 1) / kRejThreads);
+    dispatch_d(X->d, [&](auto dc) {
+        constexpr int D = decltype(dc)::value;
+        hipLaunchKernelGGL(rej_count_kernel<D>, dim3(blocks), dim3(kRejThreads), 0, s, a);
+    });
+    hipLaunchKernelGGL(rej_scan_kernel, dim3(1), dim3(1024), 0, s, a);
+    return check_launch("stratified rejection count");
+}
+
+gcp_status launch_rejection_write(const gcp_tensor* X, const gcp_sampling* cfg, int64_t ncand,
+                                  const RejScratch& rs, uint32_t* idx_out, int64_t p_off, void* xval,
+                                  uint8_t* stratum, hipStream_t s) {
+    if (cfg->q <= 0) return GCP_OK;
+    RejArgs a = rej_args(X, cfg, ncand, rs);
+    a.p_off = p_off;
     a.idx = idx_out;
     a.xval = xval;
     a.stratum = stratum;
-    a.vdtype = X->vdtype;
-    a.block_count = rs.block_count;
-    a.block_offset = rs.block_offset;
-    a.total = rs.total;
-    a.status = rs.status;
-    dispatch_d(X->d, [&](auto dc) { rejection_launch<decltype(dc)::value>(a, rs.nblk, s); });
-    return check_launch("stratified rejection");
+    const unsigned blocks = (unsigned)((ncand + kRejThreads - 1) / kRejThreads);
+    dispatch_d(X->d, [&](auto dc) {
+        constexpr int D = decltype(dc)::value;
+        hipLaunchKernelGGL(rej_write_kernel<D>, dim3(blocks), dim3(kRejThreads), 0, s, a);
+        hipLaunchKernelGGL(rej_refill_kernel<D>, dim3(1), dim3(kWave), 0, s, a);
+    });
+    return check_launch("stratified rejection write");
 }
 
 }  // namespace gcp

@@ -29,7 +29,7 @@ def test_every_declared_symbol_is_exported():
     m = _lib()
     raw = ctypes.CDLL(m.LIB_PATH)
     names = declared_functions()
-    assert len(names) >= 13
+    assert len(names) >= 16
     missing = [n for n in names if not hasattr(raw, n)]
     assert not missing, missing
     assert sorted(m.EXPORTS) == names
@@ -118,9 +118,34 @@ def test_stratified_workspace_covers_rejection_scratch():
     cfg = m.GcpSampling()
     cfg.sampler, cfg.p, cfg.q = m.STRATIFIED, 100_000, 100_000
     ws = L.gcp_sample_workspace_bytes(ctypes.byref(t), ctypes.byref(cfg))
-    nblk = math.ceil(math.ceil(1.1 * 1e5 * 4.8e8 / (4.8e8 - 959756)) / 1024)
-    assert ws >= nblk * 12
+    nchunks = math.ceil(math.ceil(1.1 * 1e5 * 4.8e8 / (4.8e8 - 959756)) / 64)
+    assert ws >= nchunks * 12
     M = m.GcpFactors()
     M.dtype, M.rank = m.F32, 8
     ws2 = L.gcp_sampled_grad_workspace_bytes(ctypes.byref(t), ctypes.byref(M), ctypes.byref(cfg))
-    assert ws2 >= ws + 2400 * 8 * 8 + 100_000 * 3 * 4
+    # every mode fits in LDS: one FP32 partial of 2400 x 8 per gradient workgroup
+    assert ws2 >= ws + 2400 * 8 * 4
+
+
+def test_sampled_adam_step_needs_factor_blocks_of_the_flat_array():
+    """The fused step updates the flat array A, so M->A[k] must be its blocks."""
+    m = _lib()
+    L = m.lib()
+    t = _dense_struct(m, (30, 40, 50))
+    cfg = m.GcpSampling()
+    cfg.sampler, cfg.s = m.UNIFORM, 100
+    M = m.GcpFactors()
+    M.dtype, M.rank = m.F32, 4
+    base = 0x10000
+    off = 0
+    for k, n in enumerate((30, 40, 50)):
+        M.A[k] = base + 4 * off
+        off += n * 4
+    def call(A):
+        return L.gcp_sampled_adam_step(0, ctypes.byref(t), ctypes.byref(M), ctypes.byref(cfg), 1e-10,
+                                       A, None, 0x40000, 0x50000, 0x60000,          # A, A_master, B, C, state
+                                       0.01, 0.9, 0.999, 1e-8, -math.inf, 0,        # Adam parameters
+                                       None, None, 0x70000, 0, None)                # G, loss_sum, ws
+    assert call(0x90000) == 1 and b"flat parameter array" in L.gcp_last_error()
+    # the right array passes the check and only then meets the (too small) workspace
+    assert call(base) == 4 and b"workspace" in L.gcp_last_error()

@@ -126,6 +126,8 @@ CASES = [
     ("counts_semi_r64_d4", lambda: small_sparse("counts", dims=(30, 7, 11, 13), rank=64)),
     ("dense_f32_d5_r16", lambda: small_dense(dims=(7, 3, 4, 6, 5), rank=16, s=1111)),
     ("dense_f64_d2_r2", lambda: small_dense(dims=(40, 31), rank=2, s=777, dtype="f64")),
+    # mode 0 (3000 x 8 FP64 = 192 KB) exceeds the LDS budget: device-atomic fallback
+    ("counts_semi_long_mode", lambda: small_sparse("counts", dims=(3000, 7, 5), rank=8, p=20000, q=30000)),
 ]
 
 
@@ -242,6 +244,32 @@ def test_adam_steps(dtype, eps_mode):
             np.testing.assert_array_equal(shadow, want)
         # continue both from the device values so every step is compared from one start
         A64 = got.copy()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_sampled_adam_step_matches_two_calls(dtype):
+    announce(f"gcp_sampled_adam_step vs gcp_sampled_grad + gcp_adam_step ({dtype})")
+    w = small_sparse("binary", rank=8)
+    pa, pb = to_device(w, dtype=dtype), to_device(w, dtype=dtype)
+    adam_a = gcp.Adam(pa.M, lr=0.01, lower=0.0)
+    adam_b = gcp.Adam(pb.M, lr=0.01, lower=0.0)
+    fused = gcp.SampledAdamStep(w.loss, pa.X, pa.M, cfg_for(pa), adam_a, keep_grad=True)
+    grad = gcp.SampledGrad(w.loss, pb.X, pb.M, cfg_for(pb))
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    for it in range(4):
+        before = (pb.M.master if dtype == "bf16" else pb.M.flat).to(torch.float64).clone()
+        fused(iteration=it)
+        grad(iteration=it)
+        adam_b.step(grad.gbuf)
+        torch.cuda.synchronize()
+        ga, gb = fused.gbuf.to(torch.float64), grad.gbuf.to(torch.float64)
+        assert float((ga - gb).norm() / gb.norm()) <= tol
+        xa = (pa.M.master if dtype == "bf16" else pa.M.flat).to(torch.float64)
+        xb = (pb.M.master if dtype == "bf16" else pb.M.flat).to(torch.float64)
+        assert float((xa - xb).norm() / (xb - before).norm()) <= tol, it
+        assert int(adam_a.state[0]) == it + 1 and int(adam_a.state[1]) == 0
+        if dtype == "bf16":
+            torch.testing.assert_close(pa.M.flat, pa.M.master.to(torch.bfloat16), rtol=0, atol=0)
 
 
 # ---------------------------------------------------------------------------
