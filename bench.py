@@ -16,6 +16,7 @@ oracle on a bounded sample of the same workload on one host core.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import math
 import os
@@ -38,6 +39,7 @@ def parse():
     ap.add_argument("--workload", default="sparse_binary_1000x800x600")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="bound on the oracle timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="launch every step eagerly")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -108,40 +110,59 @@ def main():
                            torch.as_tensor(w.coo_val).to(vdt).to(dev))
     M = gcp.Factors(w.dims, w.rank, tdt, dev, init=w.A_init)
     sampler_name = {0: "uniform", 1: "stratified", 2: "semi_stratified"}[w.sampler]
-    cfg = gcp.sampling(sampler_name, s=w.s, p=w.p, q=w.q, seed=w.seed)
+    # the device-side counter advances the sample stream on every step, so a
+    # captured graph of one step draws fresh samples on every replay
+    counter = torch.zeros(1, dtype=torch.int64, device=dev)
+    cfg = gcp.sampling(sampler_name, s=w.s, p=w.p, q=w.q, seed=w.seed, iteration_counter=counter)
     adam = gcp.Adam(M, lr=w.lr, lower=w.lower)
     step_call = gcp.SampledAdamStep(w.loss, X, M, cfg, adam)
     torch.cuda.synchronize()
     print(f"[bench] {w.name}: {w.n_samples} samples/step, nnz={w.nnz}", file=sys.stderr, flush=True)
 
-    def step(it):
-        step_call(iteration=it)
-
     for it in range(args.warmup):
-        step(it)
+        step_call()
     torch.cuda.synchronize()
 
     L = _lib.lib()
-    _lib.check(L.gcp_timing_start(args.steps))
+    kms, kn = ctypes.c_double(), ctypes.c_int64()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record()
-    for it in range(args.steps):
-        step(args.warmup + it)
-    stop.record()
-    torch.cuda.synchronize()
-    total_ms = start.elapsed_time(stop)
-    kms = ctypes_double()
-    kn = ctypes_int64()
-    _lib.check(L.gcp_timing_stop(kms, kn))
+    if args.no_graph:
+        _lib.check(L.gcp_timing_start(args.steps))
+        torch.cuda.synchronize()
+        start.record()
+        for it in range(args.steps):
+            step_call()
+        stop.record()
+        torch.cuda.synchronize()
+        total_ms = start.elapsed_time(stop)
+        _lib.check(L.gcp_timing_stop(ctypes.byref(kms), ctypes.byref(kn)))
+    else:
+        # the K timed steps as one HIP graph, replayed once in the timed region
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            for it in range(args.steps):
+                step_call()
+        torch.cuda.synchronize()
+        start.record()
+        graph.replay()
+        stop.record()
+        torch.cuda.synchronize()
+        total_ms = start.elapsed_time(stop)
+        # the gradient kernel's own duration: event pairs around it in K eager steps
+        _lib.check(L.gcp_timing_start(args.steps))
+        for it in range(args.steps):
+            step_call()
+        torch.cuda.synchronize()
+        _lib.check(L.gcp_timing_stop(ctypes.byref(kms), ctypes.byref(kn)))
     kernel_ms = kms.value / max(1, kn.value)
     ms_per_step = total_ms / args.steps
     samples = w.n_samples
     value = samples * args.steps / (total_ms / 1e3)
     balg = algorithmic_bytes(w)
     achieved = balg / (kernel_ms / 1e3) / 1e9
-    print(f"[bench] step {ms_per_step * 1e3:.1f} us, gradient kernel {kernel_ms * 1e3:.1f} us "
-          f"({kn.value} timed), {achieved:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
+    print(f"[bench] {'eager' if args.no_graph else 'graph'}: step {ms_per_step * 1e3:.1f} us, gradient kernel "
+          f"{kernel_ms * 1e3:.1f} us ({kn.value} timed), {achieved:.0f} GB/s algorithmic", file=sys.stderr,
+          flush=True)
 
     if args.copy_mib > 0:
         n = args.copy_mib * (1 << 20) // 4
@@ -179,16 +200,6 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-
-
-def ctypes_double():
-    import ctypes
-    return ctypes.c_double()
-
-
-def ctypes_int64():
-    import ctypes
-    return ctypes.c_int64()
 
 
 if __name__ == "__main__":

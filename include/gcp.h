@@ -112,6 +112,11 @@ typedef struct gcp_tensor {
     const void *nz_table;        /* COO: table from gcp_nz_index_build (needed by
                                     STRATIFIED and by UNIFORM on COO); else NULL */
     int64_t nz_slots;            /* slots of nz_table */
+    const uint32_t *nz_bitmap;   /* COO, optional: bit L of the bitmap from
+                                    gcp_nz_bitmap_build is set iff X is nonzero at
+                                    linear key L.  When given, the rejection test of
+                                    STRATIFIED reads it instead of the hash table
+                                    (one load instead of a probe sequence). */
 } gcp_tensor;
 
 /* The factor matrices A_1..A_d of the CP model (eq. Mdef). */
@@ -136,6 +141,13 @@ typedef struct gcp_sampling {
                                     first batch of ceil(rho * q * omega / zeta);
                                     rho <= 0 selects 1.1 (Sec. 4.2, App. B).  The
                                     samples never depend on rho. */
+    uint64_t *iteration_counter; /* nullable device pointer.  When set, the draws use
+                                    iteration + *iteration_counter (read on the
+                                    device) and the call adds 1 to
+                                    *iteration_counter after its last read, so a
+                                    captured HIP graph of the call draws fresh
+                                    samples on every replay.  Calls sharing a
+                                    counter must not overlap. */
 } gcp_sampling;
 
 /* Message describing the last failure on the calling thread ("" if none). */
@@ -156,6 +168,14 @@ size_t gcp_nz_table_bytes(int64_t slots);
 gcp_status gcp_nz_index_build(const gcp_tensor *X, void *table, int64_t slots,
                               hipStream_t stream);
 
+/* Exact membership bitmap of X's nonzeros: prod(dims) bits (32-bit words).
+ * gcp_nz_bitmap_bytes returns its size in bytes (0 if X is not COO);
+ * gcp_nz_bitmap_build clears and fills `bitmap` (device memory of at least
+ * that size) from X's coordinates. */
+size_t gcp_nz_bitmap_bytes(const gcp_tensor *X);
+gcp_status gcp_nz_bitmap_build(const gcp_tensor *X, uint32_t *bitmap, size_t bytes,
+                               hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
  * gcp_sample -- the sampling lines of Alg. 1 (uniform), Alg. 2 (nonzero picks
  * xi = randi(eta) and the rejection loop for zeros) and Alg. 3 (nonzero picks
@@ -164,7 +184,7 @@ gcp_status gcp_nz_index_build(const gcp_tensor *X, void *table, int64_t slots,
  *   idx[S * d]   uint32 mode indices of each sample
  *   xval[S]      X at the sample (X->vdtype); 0 for the zero strata
  *   stratum[S]   gcp_stratum code of each sample
- * STRATIFIED needs q = 0 or zeta > 0, and X->nz_table.  UNIFORM on a COO
+ * STRATIFIED needs q = 0 or zeta > 0, and X->nz_table or X->nz_bitmap.  UNIFORM on a COO
  * tensor looks values up through X->nz_table.  ws: gcp_sample_workspace_bytes
  * bytes (0 except for STRATIFIED).  The rejection loop is exact: if the first
  * candidate batch holds fewer than q zeros, a device-side loop continues the
@@ -262,9 +282,10 @@ gcp_status gcp_adam_step(int64_t P, gcp_dtype dtype, void *A, float *A_master,
  * no allocation to the calls it measures) and arms them: each following
  * gcp_sampled_grad call records one pair on its stream immediately around
  * its gradient kernel (model entries, derivatives and MTTKRP scatter), until
- * n pairs are used.  gcp_timing_stop waits for the recorded events, writes
- * the summed kernel time in milliseconds and the number of timed launches,
- * and destroys the events.  Host-global: one timing session at a time. */
+ * n pairs are used.  Calls on a stream that is being captured into a graph
+ * are not timed.  gcp_timing_stop waits for the recorded events, writes the
+ * summed kernel time in milliseconds and the number of timed launches, and
+ * destroys the events.  Host-global: one timing session at a time. */
 gcp_status gcp_timing_start(int64_t max_launches);
 gcp_status gcp_timing_stop(double *total_ms, int64_t *launches);
 

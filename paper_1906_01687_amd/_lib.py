@@ -36,7 +36,7 @@ class GcpTensor(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("format", ctypes.c_int32), ("vdtype", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("dims", ctypes.c_int64 * GCP_MAX_D),
                 ("values", ctypes.c_void_p), ("coo_idx", ctypes.c_void_p), ("nnz", ctypes.c_int64),
-                ("nz_table", ctypes.c_void_p), ("nz_slots", ctypes.c_int64)]
+                ("nz_table", ctypes.c_void_p), ("nz_slots", ctypes.c_int64), ("nz_bitmap", ctypes.c_void_p)]
 
 
 class GcpFactors(ctypes.Structure):
@@ -47,12 +47,13 @@ class GcpFactors(ctypes.Structure):
 class GcpSampling(ctypes.Structure):
     _fields_ = [("sampler", ctypes.c_int32), ("reserved", ctypes.c_int32), ("s", ctypes.c_int64),
                 ("p", ctypes.c_int64), ("q", ctypes.c_int64), ("seed", ctypes.c_uint64),
-                ("problem_id", ctypes.c_uint64), ("iteration", ctypes.c_uint64), ("rho", ctypes.c_double)]
+                ("problem_id", ctypes.c_uint64), ("iteration", ctypes.c_uint64), ("rho", ctypes.c_double),
+                ("iteration_counter", ctypes.c_void_p)]
 
 
 EXPORTS = [
     "gcp_last_error", "gcp_abi_version", "gcp_nz_table_slots", "gcp_nz_table_bytes",
-    "gcp_nz_index_build", "gcp_sample_workspace_bytes", "gcp_sample", "gcp_loss_grad",
+    "gcp_nz_index_build", "gcp_nz_bitmap_bytes", "gcp_nz_bitmap_build", "gcp_sample_workspace_bytes", "gcp_sample", "gcp_loss_grad",
     "gcp_mttkrp_workspace_bytes", "gcp_mttkrp", "gcp_sampled_grad_workspace_bytes",
     "gcp_sampled_grad", "gcp_sampled_adam_step", "gcp_adam_step", "gcp_timing_start",
     "gcp_timing_stop",
@@ -78,6 +79,8 @@ def lib() -> ctypes.CDLL:
         "gcp_nz_table_slots": (i64, [i64]),
         "gcp_nz_table_bytes": (sz, [i64]),
         "gcp_nz_index_build": (st, [T, P, i64, P]),
+        "gcp_nz_bitmap_bytes": (sz, [T]),
+        "gcp_nz_bitmap_build": (st, [T, P, sz, P]),
         "gcp_sample_workspace_bytes": (sz, [T, S]),
         "gcp_sample": (st, [T, S, P, P, P, P, sz, P]),
         "gcp_loss_grad": (st, [ctypes.c_int, T, S, M, P, P, P, i64, dbl, P, P, P]),

@@ -55,6 +55,7 @@ class DataTensor:
     coo_idx: Optional[torch.Tensor] = None      # [nnz, d] int32 (uint32 bits)
     nz_table: Optional[torch.Tensor] = None     # uint8 bytes of the nonzero hash
     nz_slots: int = 0
+    nz_bitmap: Optional[torch.Tensor] = None    # int32 words of the membership bitmap
 
     @property
     def d(self) -> int:
@@ -84,6 +85,7 @@ class DataTensor:
         t.nnz = self.nnz
         t.nz_table = _ptr(self.nz_table)
         t.nz_slots = int(self.nz_slots)
+        t.nz_bitmap = _ptr(self.nz_bitmap)
         return t
 
 
@@ -93,9 +95,14 @@ def dense_tensor(X: torch.Tensor) -> DataTensor:
     return DataTensor(tuple(X.shape), X)
 
 
+BITMAP_LIMIT_BYTES = 1 << 30
+
+
 def coo_tensor(dims: Sequence[int], coo_idx: torch.Tensor, values: torch.Tensor,
-               build_index: bool = True, stream=None) -> DataTensor:
-    """COO tensor; builds the nonzero hash (gcp_nz_index_build) unless told not to."""
+               build_index: bool = True, bitmap: Optional[bool] = None, stream=None) -> DataTensor:
+    """COO tensor; builds the nonzero hash (gcp_nz_index_build) unless told not
+    to, and the membership bitmap (gcp_nz_bitmap_build) when ``bitmap`` is True,
+    or when it is None and the bitmap takes at most BITMAP_LIMIT_BYTES."""
     if coo_idx.dtype != torch.int32 or coo_idx.dim() != 2 or coo_idx.shape[1] != len(dims):
         raise ValueError("coo_idx must be an [nnz, d] int32 tensor")
     X = DataTensor(tuple(int(n) for n in dims), values.contiguous(), coo_idx.contiguous())
@@ -106,6 +113,12 @@ def coo_tensor(dims: Sequence[int], coo_idx: torch.Tensor, values: torch.Tensor,
         t = X.struct()
         check(L.gcp_nz_index_build(ctypes.byref(t), _ptr(table), slots, _stream(stream)))
         X.nz_table, X.nz_slots = table, slots
+    t = X.struct()
+    nbytes = int(lib().gcp_nz_bitmap_bytes(ctypes.byref(t)))
+    if bitmap or (bitmap is None and 0 < nbytes <= BITMAP_LIMIT_BYTES):
+        bm = torch.empty((nbytes + 3) // 4, dtype=torch.int32, device=values.device)
+        check(lib().gcp_nz_bitmap_build(ctypes.byref(t), _ptr(bm), nbytes, _stream(stream)))
+        X.nz_bitmap = bm
     return X
 
 
@@ -166,12 +179,20 @@ class Factors:
         return m
 
 
-def sampling(sampler="uniform", s=0, p=0, q=0, seed=0, problem_id=0, iteration=0, rho=0.0) -> GcpSampling:
+def sampling(sampler="uniform", s=0, p=0, q=0, seed=0, problem_id=0, iteration=0, rho=0.0,
+             iteration_counter: Optional[torch.Tensor] = None) -> GcpSampling:
+    """A gcp_sampling struct.  ``iteration_counter`` (a 1-element int64 device
+    tensor the caller keeps alive) makes each call draw with iteration +
+    counter and then advance the counter on the device."""
     c = GcpSampling()
     c.sampler = _sampler_code(sampler)
     c.s, c.p, c.q = int(s), int(p), int(q)
     c.seed, c.problem_id, c.iteration = int(seed), int(problem_id), int(iteration)
     c.rho = float(rho)
+    if iteration_counter is not None:
+        if iteration_counter.dtype != torch.int64 or iteration_counter.numel() < 1 or not iteration_counter.is_cuda:
+            raise ValueError("iteration_counter must be an int64 device tensor")
+        c.iteration_counter = _ptr(iteration_counter)
     return c
 
 

@@ -62,12 +62,18 @@ int64_t rejection_batch(const gcp_tensor* X, const gcp_sampling* cfg) {
     return (int64_t)n;
 }
 
-RejScratch carve_rejection(Carver& c, void* base, int64_t ncand) {
+RejScratch carve_rejection(Carver& c, void* base, int64_t ncand, bool staged, int d) {
     RejScratch r{};
     r.nchunks = (ncand + kRejChunk - 1) / kRejChunk;
     if (r.nchunks < 1) r.nchunks = 1;
+    r.ngroups = (ncand + kRejThreads - 1) / kRejThreads;
+    if (r.ngroups < 1) r.ngroups = 1;
     r.chunk_count = c.take<uint32_t>(base, (size_t)r.nchunks);
     r.chunk_prefix = c.take<uint64_t>(base, (size_t)r.nchunks + 1);
+    if (staged) {
+        r.group_sum = c.take<uint32_t>(base, (size_t)r.ngroups);
+        r.zstage = c.take<uint32_t>(base, (size_t)r.nchunks * kRejChunk * (size_t)d);
+    }
     r.status = c.take<uint32_t>(base, 1);
     return r;
 }
@@ -137,7 +143,9 @@ static gcp_status check_sampling(const gcp_tensor* X, const gcp_sampling* cfg) {
         if (cfg->p < 0 || cfg->q < 0) return set_error(GCP_ERR_INVALID_ARG, "cfg->p and cfg->q must be >= 0");
         if (cfg->p > 0 && X->nnz == 0) return set_error(GCP_ERR_INVALID_ARG, "p > 0 needs at least one nonzero");
         if (cfg->sampler == GCP_SAMPLER_STRATIFIED && cfg->q > 0) {
-            if (gcp_status st = check_table(X)) return st;
+            if (!X->nz_bitmap) {
+                if (gcp_status st = check_table(X)) return st;
+            }
             const double omega = omega_d(X), zeta = omega - (double)X->nnz;
             if (!(zeta > 0.0)) return set_error(GCP_ERR_INVALID_ARG, "stratified zeros requested but X has no zeros");
             if (zeta < omega * (1.0 / 1048576.0))
@@ -174,7 +182,7 @@ static int64_t sample_count(const gcp_sampling* cfg) {
 
 static size_t sample_ws(const gcp_tensor* X, const gcp_sampling* cfg, Carver& c, void* base, RejScratch* rs) {
     if (cfg->sampler == GCP_SAMPLER_STRATIFIED && cfg->q > 0) {
-        RejScratch r = carve_rejection(c, base, rejection_batch(X, cfg));
+        RejScratch r = carve_rejection(c, base, rejection_batch(X, cfg), false, X->d);
         if (rs) *rs = r;
     }
     return c.bytes();
@@ -228,7 +236,7 @@ static size_t fused_ws(const gcp_tensor* X, const gcp_factors* M, const gcp_samp
     Carver c;
     f.acc = c.take<double>(base, (size_t)f.plan.acc_total);
     f.partials = c.take<char>(base, scatter_partials_bytes(f.plan, M->dtype));
-    if (f.rejection) f.rs = carve_rejection(c, base, f.ncand);
+    if (f.rejection) f.rs = carve_rejection(c, base, f.ncand, true, X->d);
     if (out) *out = f;
     return c.bytes();
 }
@@ -242,13 +250,21 @@ struct Timing {
 };
 static Timing g_timing;
 
+// Records nothing on a stream that is being captured into a graph: an event
+// record there would not give per-replay timings.
 static void timing_record(bool before, hipStream_t s) {
     std::lock_guard<std::mutex> lk(g_timing.mu);
     if (!g_timing.armed) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+        (void)hipGetLastError();
+        return;
+    }
     if (before) {
-        if (g_timing.used < g_timing.start.size()) (void)hipEventRecord(g_timing.start[g_timing.used], s);
+        if (g_timing.used < g_timing.start.size() && hipEventRecord(g_timing.start[g_timing.used], s) != hipSuccess)
+            (void)hipGetLastError();
     } else if (g_timing.used < g_timing.stop.size()) {
-        (void)hipEventRecord(g_timing.stop[g_timing.used], s);
+        if (hipEventRecord(g_timing.stop[g_timing.used], s) != hipSuccess) (void)hipGetLastError();
         ++g_timing.used;
     }
 }
@@ -261,17 +277,18 @@ static gcp_status sampled_common(gcp_loss loss, const gcp_tensor* X, const gcp_f
     if (!ws || ws_bytes < need) return set_error(GCP_ERR_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
     FusedLayout f{};
     fused_ws(X, M, cfg, ws, &f);
+    const bool scanned = f.rejection && f.rs.ngroups > kMaxGroupsInKernel;
     if (f.rejection) {
-        if (gcp_status st = launch_rejection_count(X, cfg, f.ncand, f.rs, stream)) return st;
+        if (gcp_status st = launch_rejection_count(X, cfg, f.ncand, f.rs, scanned, stream)) return st;
     }
     if (gcp_status st = launch_fill_zero(f.acc, f.plan.acc_total, stream)) return st;
     timing_record(true, stream);
-    const gcp_status st = launch_grad_fused(loss, X, M, cfg, eps, f.plan, f.ncand,
-                                            f.rejection ? f.rs.chunk_prefix : nullptr, f.acc, f.partials,
-                                            loss_sum, stream);
+    const gcp_status st = launch_grad_fused(loss, X, M, cfg, eps, f.plan, f.ncand, f.rejection ? &f.rs : nullptr,
+                                            scanned, f.acc, f.partials, loss_sum, adam ? adam->state : nullptr,
+                                            stream);
     timing_record(false, stream);
     if (st) return st;
-    return launch_reduce(M, f.plan, f.acc, f.partials, G, 0, adam, stream);
+    return launch_reduce(M, f.plan, f.acc, f.partials, G, 0, adam, cfg->iteration_counter, stream);
 }
 
 }  // namespace gcp
@@ -302,6 +319,27 @@ gcp_status gcp_nz_index_build(const gcp_tensor* X, void* table, int64_t slots, h
     return launch_nz_build(X, table, slots, stream);
 }
 
+size_t gcp_nz_bitmap_bytes(const gcp_tensor* X) {
+    if (!X || X->format != GCP_COO || X->d < 1 || X->d > GCP_MAX_D) return 0;
+    unsigned __int128 w = 1;
+    for (int k = 0; k < X->d; ++k) {
+        if (X->dims[k] < 1) return 0;
+        w *= (unsigned __int128)(uint64_t)X->dims[k];
+    }
+    if (w >= ((unsigned __int128)1 << 63)) return 0;
+    return (size_t)((w + 63) / 64) * 8u;
+}
+
+gcp_status gcp_nz_bitmap_build(const gcp_tensor* X, uint32_t* bitmap, size_t bytes, hipStream_t stream) {
+    clear_error();
+    if (gcp_status st = check_tensor(X)) return st;
+    if (X->format != GCP_COO) return set_error(GCP_ERR_INVALID_ARG, "gcp_nz_bitmap_build needs a COO tensor");
+    if (!bitmap) return set_error(GCP_ERR_INVALID_ARG, "bitmap is NULL");
+    const size_t need = gcp_nz_bitmap_bytes(X);
+    if (bytes < need) return set_error(GCP_ERR_INVALID_ARG, "bitmap needs " + std::to_string(need) + " bytes");
+    return launch_nz_bitmap(X, bitmap, need, stream);
+}
+
 size_t gcp_sample_workspace_bytes(const gcp_tensor* X, const gcp_sampling* cfg) {
     if (!X || !cfg) return 0;
     Carver c;
@@ -314,21 +352,30 @@ gcp_status gcp_sample(const gcp_tensor* X, const gcp_sampling* cfg, uint32_t* id
     if (gcp_status st = check_tensor(X)) return st;
     if (gcp_status st = check_sampling(X, cfg)) return st;
     const int64_t S = sample_count(cfg);
-    if (S == 0) return GCP_OK;
+    if (S == 0) return launch_bump_counter(cfg->iteration_counter, stream);
     if (!idx || !xval || !stratum) return set_error(GCP_ERR_INVALID_ARG, "idx, xval and stratum must be non-NULL");
     Carver c;
     RejScratch rs{};
     const size_t need = sample_ws(X, cfg, c, ws, &rs);
     if (need > 0 && (!ws || ws_bytes < need))
         return set_error(GCP_ERR_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
-    if (cfg->sampler == GCP_SAMPLER_UNIFORM)
-        return launch_sample_direct(X, cfg, kKindUniform, cfg->s, 0, idx, xval, stratum, stream);
-    if (gcp_status st = launch_sample_direct(X, cfg, kKindNonzero, cfg->p, 0, idx, xval, stratum, stream)) return st;
-    if (cfg->sampler == GCP_SAMPLER_SEMI_STRATIFIED)
-        return launch_sample_direct(X, cfg, kKindSemiZero, cfg->q, cfg->p, idx, xval, stratum, stream);
-    const int64_t ncand = rejection_batch(X, cfg);
-    if (gcp_status st = launch_rejection_count(X, cfg, ncand, rs, stream)) return st;
-    return launch_rejection_write(X, cfg, ncand, rs, idx, cfg->p, xval, stratum, stream);
+    if (cfg->sampler == GCP_SAMPLER_UNIFORM) {
+        if (gcp_status st = launch_sample_direct(X, cfg, kKindUniform, cfg->s, 0, idx, xval, stratum, stream))
+            return st;
+    } else {
+        if (gcp_status st = launch_sample_direct(X, cfg, kKindNonzero, cfg->p, 0, idx, xval, stratum, stream))
+            return st;
+        if (cfg->sampler == GCP_SAMPLER_SEMI_STRATIFIED) {
+            if (gcp_status st = launch_sample_direct(X, cfg, kKindSemiZero, cfg->q, cfg->p, idx, xval, stratum, stream))
+                return st;
+        } else {
+            const int64_t ncand = rejection_batch(X, cfg);
+            if (gcp_status st = launch_rejection_count(X, cfg, ncand, rs, true, stream)) return st;
+            if (gcp_status st = launch_rejection_write(X, cfg, ncand, rs, idx, cfg->p, xval, stratum, stream))
+                return st;
+        }
+    }
+    return launch_bump_counter(cfg->iteration_counter, stream);
 }
 
 gcp_status gcp_loss_grad(gcp_loss loss, const gcp_tensor* X, const gcp_sampling* cfg, const gcp_factors* M,
@@ -369,7 +416,7 @@ gcp_status gcp_mttkrp(const gcp_tensor* X, const gcp_factors* M, const uint32_t*
     mttkrp_ws(X, M, S, ws, &pl, &acc, &partials);
     if (gcp_status st = launch_fill_zero(acc, pl.acc_total, stream)) return st;
     if (gcp_status st = launch_grad_list(X, M, idx, ytilde, S, pl, acc, partials, stream)) return st;
-    return launch_reduce(M, pl, acc, partials, G, accumulate, nullptr, stream);
+    return launch_reduce(M, pl, acc, partials, G, accumulate, nullptr, nullptr, stream);
 }
 
 size_t gcp_sampled_grad_workspace_bytes(const gcp_tensor* X, const gcp_factors* M, const gcp_sampling* cfg) {

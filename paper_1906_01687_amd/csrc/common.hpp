@@ -62,11 +62,18 @@ int64_t rejection_batch(const gcp_tensor* X, const gcp_sampling* cfg);
 // Scratch of the rejection pipeline for a first batch of `ncand` candidates.
 struct RejScratch {
     uint32_t* chunk_count;   // [nchunks]
-    uint64_t* chunk_prefix;  // [nchunks + 1]: exclusive prefixes, then the total
+    uint64_t* chunk_prefix;  // [nchunks + 1]: exclusive prefixes, then the total (scan)
+    uint32_t* group_sum;     // [ngroups]: accepted per 4 chunks (fused path; else NULL)
+    uint32_t* zstage;        // [nchunks * 64 * d]: accepted indices per chunk (fused path; else NULL)
     uint32_t* status;        // [1] 0 ok, 1 refill cap reached
     int64_t nchunks;
+    int64_t ngroups;
 };
-RejScratch carve_rejection(Carver& c, void* base, int64_t ncand);
+// staged == true adds group_sum and zstage (the fused gradient path).
+RejScratch carve_rejection(Carver& c, void* base, int64_t ncand, bool staged, int d);
+// Group count up to which the fused kernel forms chunk prefixes itself
+// instead of reading a scan.
+constexpr int64_t kMaxGroupsInKernel = 2048;
 
 // Multiprocessor count of the current device (cached per device).
 int device_cu_count();
@@ -104,6 +111,7 @@ struct AdamParams {
 
 // Launchers (arguments already validated).
 gcp_status launch_nz_build(const gcp_tensor* X, void* table, int64_t slots, hipStream_t s);
+gcp_status launch_nz_bitmap(const gcp_tensor* X, uint32_t* bitmap, size_t bytes, hipStream_t s);
 
 // Direct samples c in [0, count) of one kind, written at out_off.
 enum SampleKind { kKindUniform = 0, kKindNonzero = 1, kKindSemiZero = 2 };
@@ -113,12 +121,15 @@ gcp_status launch_sample_direct(const gcp_tensor* X, const gcp_sampling* cfg, in
 
 // Chunk counts and their scan for the first rejection batch.
 gcp_status launch_rejection_count(const gcp_tensor* X, const gcp_sampling* cfg, int64_t ncand,
-                                  const RejScratch& rs, hipStream_t s);
+                                  const RejScratch& rs, bool scan, hipStream_t s);
 // Writes the first q accepted candidates' indices at idx_out + (p_off + rank) * d
 // (xval/stratum get 0 / ZERO when given), including the device-side refill.
 gcp_status launch_rejection_write(const gcp_tensor* X, const gcp_sampling* cfg, int64_t ncand,
                                   const RejScratch& rs, uint32_t* idx_out, int64_t p_off, void* xval,
                                   uint8_t* stratum, hipStream_t s);
+
+// Adds 1 to the device iteration counter (no-op for NULL).
+gcp_status launch_bump_counter(uint64_t* counter, hipStream_t s);
 
 // Stratum weights for X and cfg (omega/s, eta/p, zeta/q, eta/p, omega/q).
 void stratum_weights(const gcp_tensor* X, const gcp_sampling* cfg, double w[5]);
@@ -134,16 +145,19 @@ gcp_status launch_grad_list(const gcp_tensor* X, const gcp_factors* M, const uin
                             const void* ytilde, int64_t S, const ScatterPlan& pl, double* acc,
                             void* partials, hipStream_t s);
 
+// adam_state (nullable): the gradient kernel advances the Adam step count
+// state[0] by one; the reduction that follows reads the new value.
 gcp_status launch_grad_fused(gcp_loss loss, const gcp_tensor* X, const gcp_factors* M,
                              const gcp_sampling* cfg, double eps, const ScatterPlan& pl, int64_t ncand,
-                             const uint64_t* chunk_prefix, double* acc, void* partials,
-                             double* loss_sum, hipStream_t s);
+                             const RejScratch* rs, bool scanned, double* acc, void* partials,
+                             double* loss_sum, int64_t* adam_state, hipStream_t s);
 
 // G[k] (nullable entries) from partials and accumulator; with adam != NULL the
 // Adam step is applied to the same elements in the same kernel.
+// A non-NULL bump_counter is incremented by the reduction (after every read).
 gcp_status launch_reduce(const gcp_factors* M, const ScatterPlan& pl, const double* acc,
                          const void* partials, void* const* G, int accumulate, const AdamParams* adam,
-                         hipStream_t s);
+                         uint64_t* bump_counter, hipStream_t s);
 
 gcp_status launch_adam(int64_t P, gcp_dtype dtype, void* A, float* A_master, const void* G,
                        void* B, void* C, int64_t* state, double alpha, double beta1, double beta2,

@@ -66,6 +66,13 @@ __device__ __forceinline__ void draw_index(uint64_t seed, uint64_t pid, uint64_t
     }
 }
 
+// The iteration a launch draws with: the host value plus, when given, the
+// device-side counter (read once per thread; the counter only changes in a
+// later kernel of the same call).
+__device__ __forceinline__ uint64_t effective_iteration(uint64_t base, const uint64_t* counter) {
+    return counter ? base + *counter : base;
+}
+
 // Nonzero pick xi = randi(eta) from word 0 of the purpose-1 stream.
 __device__ __forceinline__ uint64_t draw_nonzero(uint64_t seed, uint64_t pid, uint64_t j,
                                                  uint64_t iter, uint64_t nnz) {
@@ -96,6 +103,7 @@ struct NzTable {
     const uint64_t* keys;
     const uint32_t* pos;
     uint64_t mask;
+    const uint32_t* bitmap;  // optional exact membership bitmap (bit L set iff nonzero)
 };
 
 // COO position of linear key L, or -1 if X is zero there.
@@ -111,12 +119,19 @@ __device__ __forceinline__ int64_t nz_find(const NzTable& t, uint64_t L) {
     return -1;
 }
 
+// Whether X is nonzero at linear key L: one bitmap load when the bitmap
+// exists, else the hash probe sequence.
+__device__ __forceinline__ bool nz_member(const NzTable& t, uint64_t L) {
+    if (t.bitmap) return (t.bitmap[L >> 5] >> (L & 31)) & 1u;
+    return nz_find(t, L) >= 0;
+}
+
 // Rejection candidate j (purpose 2): its indices, and whether X is zero there.
 template <int D>
 __device__ __forceinline__ bool candidate_accepted(const Dims& dims, const NzTable& tab, uint64_t seed,
                                                    uint64_t pid, uint64_t iter, uint64_t j, uint32_t (&i)[D]) {
     draw_index<D>(seed, pid, j, iter, kPurposeCandidate, dims.n, i);
-    return nz_find(tab, linear_key<D>(i, dims.n)) < 0;
+    return !nz_member(tab, linear_key<D>(i, dims.n));
 }
 
 // ---------------------------------------------------------------------------

@@ -49,14 +49,18 @@ struct GradArgs {
     int lps;
     int64_t nnz;
     uint64_t seed, pid, iter;
+    const uint64_t* iter_ctr;
     const void* values;
     const uint32_t* coo;
     NzTable tab;
     // direct items: samples c in [0, n_direct), 64 per item
     int64_t n_direct, n_direct_items, p;
     // stratified zeros: one item per chunk of 64 rejection candidates
-    int64_t n_zero_items, ncand, q;
-    const uint64_t* chunk_prefix;
+    int64_t n_zero_items, ncand, q, ngroups;
+    const uint32_t* chunk_count;
+    const uint32_t* group_sum;
+    const uint32_t* zstage;
+    const uint64_t* chunk_prefix;  // non-NULL when a scan provided the prefixes
     // list mode (gcp_mttkrp): indices and ytilde per sample
     const uint32_t* idx;
     const void* ytilde;
@@ -71,6 +75,7 @@ struct GradArgs {
     double w[5];
     double eps;
     double* loss_sum;
+    int64_t* adam_state;  // fused step: state[0] += 1 here, read by the reduction
 };
 
 struct ReduceArgs {
@@ -78,6 +83,8 @@ struct ReduceArgs {
     int accumulate;
     int64_t P;
     int64_t off[GCP_MAX_D + 1];
+    int64_t blk_start[GCP_MAX_D + 1];  // first workgroup of mode k; [d] = grid size
+    uint64_t* bump_counter;
     uint32_t priv_mask;
     int64_t lds_off[GCP_MAX_D];
     int64_t lds_total;
@@ -113,10 +120,11 @@ __device__ __forceinline__ T pick_weight(const double (&w)[5], int code) {
 
 // Phase A for direct items: sample c's indices, data value and stratum.
 template <int D, typename VT, typename T>
-__device__ __forceinline__ void produce(const GradArgs& a, int64_t c, uint32_t (&i)[D], T& x, int& code) {
+__device__ __forceinline__ void produce(const GradArgs& a, uint64_t iter, int64_t c, uint32_t (&i)[D], T& x,
+                                        int& code) {
     const VT* __restrict__ vals = static_cast<const VT*>(a.values);
     if (a.sampler == GCP_SAMPLER_UNIFORM) {
-        draw_index<D>(a.seed, a.pid, (uint64_t)c, a.iter, kPurposeUniform, a.dims.n, i);
+        draw_index<D>(a.seed, a.pid, (uint64_t)c, iter, kPurposeUniform, a.dims.n, i);
         const uint64_t L = linear_key<D>(i, a.dims.n);
         if (a.format == GCP_DENSE) {
             x = (T)vals[L];
@@ -126,20 +134,24 @@ __device__ __forceinline__ void produce(const GradArgs& a, int64_t c, uint32_t (
         }
         code = GCP_STRATUM_UNIFORM;
     } else if (c < a.p) {
-        const uint64_t e = draw_nonzero(a.seed, a.pid, (uint64_t)c, a.iter, (uint64_t)a.nnz);
+        const uint64_t e = draw_nonzero(a.seed, a.pid, (uint64_t)c, iter, (uint64_t)a.nnz);
 #pragma unroll
         for (int k = 0; k < D; ++k) i[k] = a.coo[e * D + k];
         x = (T)vals[e];
         code = a.sampler == GCP_SAMPLER_SEMI_STRATIFIED ? GCP_STRATUM_NZ_CORR : GCP_STRATUM_NZ;
     } else {
-        draw_index<D>(a.seed, a.pid, (uint64_t)(c - a.p), a.iter, kPurposeUniform, a.dims.n, i);
+        draw_index<D>(a.seed, a.pid, (uint64_t)(c - a.p), iter, kPurposeUniform, a.dims.n, i);
         x = T(0);
         code = GCP_STRATUM_SEMI_ZERO;
     }
 }
 
 // Phase B: the wave's 64 samples (one per lane in i/x/code/ylist) are
-// evaluated and scattered.  Every lane of the wave must call this.
+// evaluated and scattered.  Every lane of the wave must call this.  Passes
+// are taken kBatch at a time so that the row gathers of a batch are all in
+// flight before any of them is consumed.
+constexpr int kBatch = 4;
+
 template <int D, typename FT, bool LIST>
 __device__ __forceinline__ void evaluate_and_scatter(const GradArgs& a, double* __restrict__ lds,
                                                      const uint32_t (&i)[D],
@@ -154,59 +166,94 @@ __device__ __forceinline__ void evaluate_and_scatter(const GradArgs& a, double* 
     const int j = lane & (lps - 1);
     const int r = a.r;
     const T eps = (T)a.eps;
-    for (int pass = 0; pass < lps; ++pass) {
-        const int src = pass * spw + slot;
-        uint32_t ii[D];
+    for (int p0 = 0; p0 < lps; p0 += kBatch) {
+        uint32_t ii[kBatch][D];
+        int cc[kBatch];
+        T xx[kBatch], yy[kBatch];
 #pragma unroll
-        for (int k = 0; k < D; ++k) ii[k] = __shfl(i[k], src);
-        const int cc = __shfl(code, src);
-        const bool live = cc >= 0;
-        const bool col = live && j < r;
-        T av[D];
+        for (int u = 0; u < kBatch; ++u) {
+            const int pass = p0 + u < lps ? p0 + u : 0;
+            const int src = pass * spw + slot;
 #pragma unroll
-        for (int k = 0; k < D; ++k)
-            av[k] = col ? widen(static_cast<const FT*>(a.A[k])[(size_t)ii[k] * r + j]) : T(0);
-        T pre[D], suf[D];
-        pre[0] = T(1);
-#pragma unroll
-        for (int k = 1; k < D; ++k) pre[k] = pre[k - 1] * av[k - 1];
-        suf[D - 1] = T(1);
-#pragma unroll
-        for (int k = D - 2; k >= 0; --k) suf[k] = suf[k + 1] * av[k + 1];
-        T y;
-        if constexpr (LIST) {
-            y = __shfl(ylist, src);
-        } else {
-            T m = pre[D - 1] * av[D - 1];
-            for (int o = lps >> 1; o > 0; o >>= 1) m += __shfl_xor(m, o);
-            const T xx = __shfl(x, src);
-            const T w = pick_weight<T>(a.w, cc);
-            T g = loss_g<T>(a.loss, xx, m, eps);
-            const bool corr = cc == GCP_STRATUM_NZ_CORR;
-            if (corr) g -= loss_g<T>(a.loss, T(0), m, eps);
-            y = w * g;
-            if (a.loss_sum && live && j == 0) {
-                T f = loss_f<T>(a.loss, xx, m, eps);
-                if (corr) f -= loss_f<T>(a.loss, T(0), m, eps);
-                fsum += w * f;
-            }
+            for (int k = 0; k < D; ++k) ii[u][k] = __shfl(i[k], src);
+            cc[u] = p0 + u < lps ? __shfl(code, src) : -1;
+            if constexpr (LIST) yy[u] = __shfl(ylist, src);
+            else xx[u] = __shfl(x, src);
         }
-        if (col) {
+        T av[kBatch][D];
 #pragma unroll
-            for (int k = 0; k < D; ++k) {
-                const double v = (double)(y * pre[k] * suf[k]);
-                if ((a.priv_mask >> k) & 1u)
-                    atomicAdd(&lds[a.lds_off[k] + (int64_t)ii[k] * r + j], v);
-                else
-                    unsafeAtomicAdd(&a.acc[a.acc_off[k] + (int64_t)ii[k] * r + j], v);
+        for (int u = 0; u < kBatch; ++u) {
+            const bool col = cc[u] >= 0 && j < r;
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+                av[u][k] = col ? widen(static_cast<const FT*>(a.A[k])[(size_t)ii[u][k] * r + j]) : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const bool live = cc[u] >= 0;
+            const bool col = live && j < r;
+            T pre[D], suf[D];
+            pre[0] = T(1);
+#pragma unroll
+            for (int k = 1; k < D; ++k) pre[k] = pre[k - 1] * av[u][k - 1];
+            suf[D - 1] = T(1);
+#pragma unroll
+            for (int k = D - 2; k >= 0; --k) suf[k] = suf[k + 1] * av[u][k + 1];
+            T y;
+            if constexpr (LIST) {
+                y = yy[u];
+            } else {
+                T m = pre[D - 1] * av[u][D - 1];
+                for (int o = lps >> 1; o > 0; o >>= 1) m += __shfl_xor(m, o);
+                const T w = pick_weight<T>(a.w, cc[u]);
+                T g = loss_g<T>(a.loss, xx[u], m, eps);
+                const bool corr = cc[u] == GCP_STRATUM_NZ_CORR;
+                if (corr) g -= loss_g<T>(a.loss, T(0), m, eps);
+                y = w * g;
+                if (a.loss_sum && live && j == 0) {
+                    T f = loss_f<T>(a.loss, xx[u], m, eps);
+                    if (corr) f -= loss_f<T>(a.loss, T(0), m, eps);
+                    fsum += w * f;
+                }
+            }
+            if (col) {
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    const double v = (double)(y * pre[k] * suf[k]);
+                    if ((a.priv_mask >> k) & 1u)
+                        atomicAdd(&lds[a.lds_off[k] + (int64_t)ii[u][k] * r + j], v);
+                    else
+                        unsafeAtomicAdd(&a.acc[a.acc_off[k] + (int64_t)ii[u][k] * r + j], v);
+                }
             }
         }
     }
 }
 
-// Exclusive prefix of a zero chunk.
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Exclusive prefix of zero chunk `chunk` (wave-uniform): from the scan when
+// there is one, else from the per-group sums of the count kernel.
 __device__ __forceinline__ uint64_t chunk_prefix(const GradArgs& a, int64_t chunk) {
-    return a.chunk_prefix[chunk];
+    if (a.chunk_prefix) return a.chunk_prefix[chunk];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t g = chunk / (kRejThreads / kWave);
+    uint64_t s = 0;
+    for (int64_t b = lane; b < g; b += kWave) s += a.group_sum[b];
+    if (lane < chunk - g * (kRejThreads / kWave)) s += a.chunk_count[g * (kRejThreads / kWave) + lane];
+    return wave_sum_u64(s);
+}
+
+// Accepted candidates in the whole first batch (wave-uniform).
+__device__ __forceinline__ uint64_t batch_total(const GradArgs& a) {
+    if (a.chunk_prefix) return a.chunk_prefix[a.n_zero_items];
+    const int lane = threadIdx.x & (kWave - 1);
+    uint64_t s = 0;
+    for (int64_t b = lane; b < a.ngroups; b += kWave) s += a.group_sum[b];
+    return wave_sum_u64(s);
 }
 
 template <int D, typename FT, typename VT, bool LIST>
@@ -215,12 +262,15 @@ __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
     extern __shared__ double lds[];
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t nthreads = blockDim.x;
+    // nothing in this kernel reads the step count; the reduction after it does
+    if (a.adam_state && blockIdx.x == 0 && threadIdx.x == 0) a.adam_state[0] += 1;
     for (int64_t e = threadIdx.x; e < a.lds_total; e += nthreads) lds[e] = 0.0;
     __syncthreads();
 
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
     const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) / kWave;
     const int64_t n_items = a.n_direct_items + a.n_zero_items;
+    const uint64_t iter = effective_iteration(a.iter, a.iter_ctr);
     T fsum = T(0);
 
     for (int64_t item = wave; item < n_items; item += nwave) {
@@ -238,26 +288,29 @@ __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
                     ylist = static_cast<const T*>(a.ytilde)[c];
                     code = 0;
                 } else {
-                    produce<D, VT, T>(a, c, i, x, code);
+                    produce<D, VT, T>(a, iter, c, i, x, code);
                 }
             }
             evaluate_and_scatter<D, FT, LIST>(a, lds, i, x, code, ylist, fsum);
         } else if constexpr (!LIST) {
-            // stratified zeros: one chunk of 64 rejection candidates
+            // stratified zeros: the accepted candidates of one 64-candidate chunk,
+            // staged in counter order by the count kernel
             const int64_t chunk = item - a.n_direct_items;
-            const uint64_t j = (uint64_t)chunk * kWave + lane;
-            const bool acc = j < (uint64_t)a.ncand && candidate_accepted<D>(a.dims, a.tab, a.seed, a.pid, a.iter, j, i);
-            const uint64_t bal = __ballot(acc);
-            const uint64_t rank = chunk_prefix(a, chunk) + __popcll(bal & ((1ull << lane) - 1ull));
-            code = (acc && rank < (uint64_t)a.q) ? GCP_STRATUM_ZERO : -1;
+            const uint64_t rank = chunk_prefix(a, chunk) + (uint64_t)lane;
+            const uint32_t cnt = a.chunk_count[chunk];
+            if ((uint32_t)lane < cnt && rank < (uint64_t)a.q) {
+#pragma unroll
+                for (int k = 0; k < D; ++k) i[k] = a.zstage[((int64_t)chunk * kWave + lane) * D + k];
+                code = GCP_STRATUM_ZERO;
+            }
             evaluate_and_scatter<D, FT, false>(a, lds, i, x, code, ylist, fsum);
             if (chunk == a.n_zero_items - 1) {
                 // first batch short of q zeros: continue the counter stream (wave-uniform loop)
-                uint64_t filled = a.chunk_prefix[a.n_zero_items];
+                uint64_t filled = batch_total(a);
                 uint64_t base = (uint64_t)a.ncand;
                 for (int64_t t = 0; t < kRejMaxRefillTiles * 16 && filled < (uint64_t)a.q; ++t) {
                     const uint64_t jj = base + lane;
-                    const bool ok = candidate_accepted<D>(a.dims, a.tab, a.seed, a.pid, a.iter, jj, i);
+                    const bool ok = candidate_accepted<D>(a.dims, a.tab, a.seed, a.pid, iter, jj, i);
                     const uint64_t b2 = __ballot(ok);
                     const uint64_t rk = filled + __popcll(b2 & ((1ull << lane) - 1ull));
                     const int cz = (ok && rk < (uint64_t)a.q) ? GCP_STRATUM_ZERO : -1;
@@ -338,100 +391,121 @@ __global__ __launch_bounds__(256) void loss_grad_kernel(LossArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Reduction: G = sum of the per-workgroup partials (fixed order, FP64) for
-// privatised modes, the FP64 accumulator for the others; optionally the Adam
-// step on the same elements.  Elements are numbered over all modes in mode
-// order (the flat parameter layout), 64 per workgroup; the 16 waves of a
-// workgroup each sum every 16th partial and the wave sums are combined in
-// wave order.
+// Reduction: G = the sum of the per-workgroup partials (fixed order, FP64)
+// for privatised modes and the FP64 accumulator for the others, optionally
+// followed by the Adam step on the same elements.  Elements are numbered over
+// all modes in mode order (the flat parameter layout).  A privatised mode
+// gets workgroups of 64 elements whose 16 waves each sum every 16th partial
+// (combined in wave order); an accumulator mode gets 1024 elements per
+// workgroup, one per thread.
 // ---------------------------------------------------------------------------
 constexpr int kRedWaves = 16;
+constexpr int kRedThreads = kRedWaves * kWave;
 
 template <typename GT, int ADAM>
-__global__ __launch_bounds__(kRedWaves * kWave) void reduce_kernel(ReduceArgs a) {
-    __shared__ double wave_sum[kRedWaves][kWave];
-    __shared__ int64_t t_shared;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wv = threadIdx.x / kWave;
-    const int64_t e = (int64_t)blockIdx.x * kWave + lane;
-    const bool in = e < a.P;
-    int k = 0;
+__device__ __forceinline__ void finish_element(const ReduceArgs& a, int k, int64_t local, double g, int64_t t,
+                                               double bc1d, double bc2d) {
+    const int64_t e = a.off[k] + local;
+    void* gk = a.G[0];
 #pragma unroll
-    for (int t = 1; t < GCP_MAX_D; ++t)
-        if (t < a.d && e >= a.off[t]) k = t;
-    const int64_t local = in ? e - a.off[k] : 0;
-    const bool priv = (a.priv_mask >> k) & 1u;
-    double s = 0.0;
-    if (in && priv) {
-        const int64_t pe = a.lds_off[k] + local;
-        const GT* __restrict__ parts = static_cast<const GT*>(a.partials);  // partial type = gradient type
-        for (int64_t b = wv; b < a.nparts; b += kRedWaves) s += (double)parts[b * a.lds_total + pe];
-    }
-    wave_sum[wv][lane] = s;
-    if (ADAM && threadIdx.x == 0) t_shared = a.state[0] + 1;
-    __syncthreads();
-    if (wv == 0) {
-        double g = 0.0;
-        if (priv) {
-#pragma unroll
-            for (int w = 0; w < kRedWaves; ++w) g += wave_sum[w][lane];
-        } else if (in) {
-            g = a.acc[a.acc_off[k] + local];
-        }
-        if (in) {
-            void* gk = a.G[0];
-#pragma unroll
-            for (int t = 1; t < GCP_MAX_D; ++t)
-                if (t == k) gk = a.G[t];
-            if (gk) {
-                GT* Gp = static_cast<GT*>(gk);
-                double v = g;
-                if (a.accumulate) v += (double)Gp[local];
-                Gp[local] = (GT)v;
-            }
-        }
-        if constexpr (ADAM != 0) {
-            if (in) {
-                using T = GT;  // moment type: double for F64 factors, float otherwise
-                const int64_t t = t_shared;
-                const T gt = (T)g;
-                const T b1 = (T)a.beta1, b2 = (T)a.beta2;
-                const T omb1 = (T)(1.0 - a.beta1), omb2 = (T)(1.0 - a.beta2);
-                const T bc1 = (T)(1.0 - pow(a.beta1, (double)t));
-                const T bc2 = (T)(1.0 - pow(a.beta2, (double)t));
-                T* B = static_cast<T*>(a.B);
-                T* C = static_cast<T*>(a.C);
-                const T bm = b1 * B[e] + omb1 * gt;
-                const T cm = b2 * C[e] + omb2 * gt * gt;
-                B[e] = bm;
-                C[e] = cm;
-                const T bhat = bm / bc1, chat = cm / bc2;
-                const T den = a.eps_mode == GCP_EPS_INSIDE_SQRT ? sqrt(chat + (T)a.eps) : sqrt(chat) + (T)a.eps;
-                const T step = (T)a.alpha * bhat / den;
-                if constexpr (ADAM == 2) {
-                    float v = a.A_master[e] - (float)step;
-                    v = v < (float)a.lower ? (float)a.lower : v;
-                    a.A_master[e] = v;
-                    static_cast<bf16_t*>(a.A)[e] = to_bf16(v);
-                } else {
-                    T* A = static_cast<T*>(a.A);
-                    T v = A[e] - step;
-                    A[e] = v < (T)a.lower ? (T)a.lower : v;
-                }
-            }
-        }
+    for (int q = 1; q < GCP_MAX_D; ++q)
+        if (q == k) gk = a.G[q];
+    if (gk) {
+        GT* Gp = static_cast<GT*>(gk);
+        double v = g;
+        if (a.accumulate) v += (double)Gp[local];
+        Gp[local] = (GT)v;
     }
     if constexpr (ADAM != 0) {
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            __threadfence();
-            const unsigned long long done =
-                atomicAdd(reinterpret_cast<unsigned long long*>(&a.state[1]), 1ull);
-            if (done == (unsigned long long)gridDim.x - 1ull) {
-                a.state[0] = t_shared;
-                a.state[1] = 0;
-            }
+        using T = GT;  // moment type: double for F64 factors, float otherwise
+        const T gt = (T)g;
+        const T b1 = (T)a.beta1, b2 = (T)a.beta2;
+        const T omb1 = (T)(1.0 - a.beta1), omb2 = (T)(1.0 - a.beta2);
+        const T bc1 = (T)bc1d, bc2 = (T)bc2d;
+        T* B = static_cast<T*>(a.B);
+        T* C = static_cast<T*>(a.C);
+        const T bm = b1 * B[e] + omb1 * gt;
+        const T cm = b2 * C[e] + omb2 * gt * gt;
+        B[e] = bm;
+        C[e] = cm;
+        const T bhat = bm / bc1, chat = cm / bc2;
+        const T den = a.eps_mode == GCP_EPS_INSIDE_SQRT ? sqrt(chat + (T)a.eps) : sqrt(chat) + (T)a.eps;
+        const T step = (T)a.alpha * bhat / den;
+        if constexpr (ADAM == 2) {
+            float v = a.A_master[e] - (float)step;
+            v = v < (float)a.lower ? (float)a.lower : v;
+            a.A_master[e] = v;
+            static_cast<bf16_t*>(a.A)[e] = to_bf16(v);
+        } else {
+            T* A = static_cast<T*>(a.A);
+            T v = A[e] - step;
+            A[e] = v < (T)a.lower ? (T)a.lower : v;
         }
+    }
+    (void)t;
+}
+
+template <typename GT, int ADAM>
+__global__ __launch_bounds__(kRedThreads) void reduce_kernel(ReduceArgs a) {
+    __shared__ double wave_sum[kRedWaves][kWave];
+    __shared__ int64_t t_shared;
+    __shared__ double bc_shared[2];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    int k = 0;
+#pragma unroll
+    for (int q = 1; q < GCP_MAX_D; ++q)
+        if (q < a.d && (int64_t)blockIdx.x >= a.blk_start[q]) k = q;
+    const int64_t lb = (int64_t)blockIdx.x - a.blk_start[k];
+    const int64_t nk = a.off[k + 1] - a.off[k];
+    const bool priv = (a.priv_mask >> k) & 1u;
+    // every earlier kernel of the call has read the iteration counter
+    if (a.bump_counter && blockIdx.x == 0 && threadIdx.x == 0) a.bump_counter[0] += 1;
+    if (ADAM && threadIdx.x == 0) {
+        const int64_t t = a.state[0];  // already advanced by the gradient kernel
+        t_shared = t;
+        bc_shared[0] = 1.0 - pow(a.beta1, (double)t);
+        bc_shared[1] = 1.0 - pow(a.beta2, (double)t);
+    }
+    if (priv) {
+        const int64_t local = lb * kWave + lane;
+        const bool in = local < nk;
+        double s = 0.0;
+        if (in) {
+            // eight independent partial sums keep eight loads in flight; they are
+            // combined in a fixed order, so the result does not depend on timing
+            const int64_t pe = a.lds_off[k] + local;
+            const GT* __restrict__ parts = static_cast<const GT*>(a.partials);  // partial type = gradient type
+            constexpr int U = 8;
+            double acc8[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc8[u] = 0.0;
+            int64_t b = wv;
+            for (; b + (U - 1) * kRedWaves < a.nparts; b += U * kRedWaves) {
+                GT v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) v[u] = parts[(b + u * kRedWaves) * a.lds_total + pe];
+#pragma unroll
+                for (int u = 0; u < U; ++u) acc8[u] += (double)v[u];
+            }
+            for (; b < a.nparts; b += kRedWaves) acc8[0] += (double)parts[b * a.lds_total + pe];
+            s = ((acc8[0] + acc8[1]) + (acc8[2] + acc8[3])) + ((acc8[4] + acc8[5]) + (acc8[6] + acc8[7]));
+        }
+        wave_sum[wv][lane] = s;
+        __syncthreads();
+        if (wv == 0 && in) {
+            double g = 0.0;
+#pragma unroll
+            for (int w = 0; w < kRedWaves; ++w) g += wave_sum[w][lane];
+            finish_element<GT, ADAM>(a, k, local, g, ADAM ? t_shared : 0, ADAM ? bc_shared[0] : 1.0,
+                                     ADAM ? bc_shared[1] : 1.0);
+        }
+    } else {
+        __syncthreads();
+        const int64_t local = lb * kRedThreads + threadIdx.x;
+        if (local < nk)
+            finish_element<GT, ADAM>(a, k, local, a.acc[a.acc_off[k] + local], ADAM ? t_shared : 0,
+                                     ADAM ? bc_shared[0] : 1.0, ADAM ? bc_shared[1] : 1.0);
     }
 }
 
@@ -567,6 +641,7 @@ static GradArgs base_args(const gcp_tensor* X, const gcp_factors* M, const Scatt
         a.tab.pos = reinterpret_cast<const uint32_t*>(static_cast<const char*>(X->nz_table) + 8 * X->nz_slots);
         a.tab.mask = (uint64_t)X->nz_slots - 1;
     }
+    a.tab.bitmap = X->nz_bitmap;
     for (int k = 0; k < X->d; ++k) {
         a.A[k] = M->A[k];
         a.lds_off[k] = pl.lds_off[k];
@@ -598,17 +673,20 @@ int64_t fused_items(const gcp_sampling* cfg, int64_t ncand) {
 }
 
 gcp_status launch_grad_fused(gcp_loss loss, const gcp_tensor* X, const gcp_factors* M, const gcp_sampling* cfg,
-                             double eps, const ScatterPlan& pl, int64_t ncand, const uint64_t* chunk_prefix,
-                             double* acc, void* partials, double* loss_sum, hipStream_t s) {
+                             double eps, const ScatterPlan& pl, int64_t ncand, const RejScratch* rs,
+                             bool scanned, double* acc, void* partials, double* loss_sum, int64_t* adam_state,
+                             hipStream_t s) {
     GradArgs a = base_args(X, M, pl, acc, partials);
     a.loss = loss;
     a.sampler = cfg->sampler;
     a.seed = cfg->seed;
     a.pid = cfg->problem_id;
     a.iter = cfg->iteration;
+    a.iter_ctr = cfg->iteration_counter;
     stratum_weights(X, cfg, a.w);
     a.eps = eps;
     a.loss_sum = loss_sum;
+    a.adam_state = adam_state;
     if (cfg->sampler == GCP_SAMPLER_UNIFORM) {
         a.n_direct = cfg->s;
         a.p = 0;
@@ -620,8 +698,14 @@ gcp_status launch_grad_fused(gcp_loss loss, const gcp_tensor* X, const gcp_facto
         a.p = cfg->p;
         a.q = cfg->q;
         a.ncand = ncand;
-        a.chunk_prefix = chunk_prefix;
-        a.n_zero_items = cfg->q > 0 ? (ncand + kWave - 1) / kWave : 0;
+        if (rs && cfg->q > 0) {
+            a.chunk_count = rs->chunk_count;
+            a.group_sum = rs->group_sum;
+            a.zstage = rs->zstage;
+            a.ngroups = rs->ngroups;
+            a.chunk_prefix = scanned ? rs->chunk_prefix : nullptr;
+            a.n_zero_items = rs->nchunks;
+        }
     }
     a.n_direct_items = (a.n_direct + kWave - 1) / kWave;
     // with nothing sampled the single workgroup still publishes a zero partial
@@ -630,8 +714,10 @@ gcp_status launch_grad_fused(gcp_loss loss, const gcp_tensor* X, const gcp_facto
 }
 
 gcp_status launch_reduce(const gcp_factors* M, const ScatterPlan& pl, const double* acc, const void* partials,
-                         void* const* G, int accumulate, const AdamParams* adam, hipStream_t s) {
+                         void* const* G, int accumulate, const AdamParams* adam, uint64_t* bump_counter,
+                         hipStream_t s) {
     ReduceArgs a{};
+    a.bump_counter = bump_counter;
     a.d = pl.d;
     a.P = pl.P;
     for (int k = 0; k <= GCP_MAX_D; ++k) a.off[k] = pl.off[k];
@@ -659,8 +745,15 @@ gcp_status launch_reduce(const gcp_factors* M, const ScatterPlan& pl, const doub
         a.lower = adam->lower;
         a.eps_mode = adam->eps_mode;
     }
-    if (pl.P <= 0) return GCP_OK;
-    const dim3 g((unsigned)((pl.P + kWave - 1) / kWave)), b(kRedWaves * kWave);
+    if (pl.P <= 0) return launch_bump_counter(bump_counter, s);
+    int64_t nb = 0;
+    for (int k = 0; k < pl.d; ++k) {
+        a.blk_start[k] = nb;
+        const int64_t nk = pl.off[k + 1] - pl.off[k];
+        nb += ((pl.priv_mask >> k) & 1u) ? (nk + kWave - 1) / kWave : (nk + kRedThreads - 1) / kRedThreads;
+    }
+    for (int k = pl.d; k <= GCP_MAX_D; ++k) a.blk_start[k] = nb;
+    const dim3 g((unsigned)nb), b(kRedThreads);
     const bool f64 = M->dtype == GCP_F64;
     if (!adam) {
         if (f64) hipLaunchKernelGGL((reduce_kernel<double, 0>), g, b, 0, s, a);

@@ -47,12 +47,25 @@ __global__ void nz_build_kernel(const uint32_t* __restrict__ coo, int64_t nnz, D
     }
 }
 
+template <int D>
+__global__ void nz_bitmap_kernel(const uint32_t* __restrict__ coo, int64_t nnz, Dims dims, uint32_t* bitmap) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t i[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) i[k] = coo[e * D + k];
+        const uint64_t L = linear_key<D>(i, dims.n);
+        atomicOr(&bitmap[L >> 5], 1u << (L & 31));
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Direct draws: uniform, nonzero picks, semi-stratified zeros.
 // ---------------------------------------------------------------------------
 struct DirectArgs {
     Dims dims;
     uint64_t seed, pid, iter;
+    const uint64_t* iter_ctr;
     int kind;
     int format;
     int64_t count, out_off, nnz;
@@ -69,19 +82,20 @@ template <int D, typename VT>
 __global__ void sample_direct_kernel(DirectArgs a) {
     const VT* __restrict__ vals = static_cast<const VT*>(a.values);
     VT* __restrict__ xout = static_cast<VT*>(a.xval);
+    const uint64_t iter = effective_iteration(a.iter, a.iter_ctr);
     for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < a.count;
          c += (int64_t)gridDim.x * blockDim.x) {
         uint32_t i[D];
         VT x = VT(0);
         uint8_t code;
         if (a.kind == kKindNonzero) {
-            const uint64_t e = draw_nonzero(a.seed, a.pid, (uint64_t)c, a.iter, (uint64_t)a.nnz);
+            const uint64_t e = draw_nonzero(a.seed, a.pid, (uint64_t)c, iter, (uint64_t)a.nnz);
 #pragma unroll
             for (int k = 0; k < D; ++k) i[k] = a.coo[e * D + k];
             x = vals[e];
             code = a.nz_code;
         } else {
-            draw_index<D>(a.seed, a.pid, (uint64_t)c, a.iter, kPurposeUniform, a.dims.n, i);
+            draw_index<D>(a.seed, a.pid, (uint64_t)c, iter, kPurposeUniform, a.dims.n, i);
             if (a.kind == kKindUniform) {
                 const uint64_t L = linear_key<D>(i, a.dims.n);
                 if (a.format == GCP_DENSE) {
@@ -111,6 +125,7 @@ __global__ void sample_direct_kernel(DirectArgs a) {
 struct RejArgs {
     Dims dims;
     uint64_t seed, pid, iter;
+    const uint64_t* iter_ctr;
     int64_t ncand;  // candidates in the first batch
     int64_t q;      // zeros wanted
     int64_t p_off;  // output offset of zero 0
@@ -121,18 +136,43 @@ struct RejArgs {
     int vdtype;
     uint32_t* chunk_count;
     uint64_t* chunk_prefix;
+    uint32_t* group_sum;
+    uint32_t* zstage;
     uint32_t* status;
     int64_t nchunks;
 };
 
+// Counts the accepted candidates of each 64-candidate chunk, stages their
+// indices compacted in counter order (zstage[chunk * 64 + rank][k]) and
+// writes the sum of each workgroup's 4 chunks (group_sum).
 template <int D>
 __global__ __launch_bounds__(kRejThreads) void rej_count_kernel(RejArgs a) {
+    __shared__ uint32_t wave_cnt[kRejThreads / kWave];
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t iter = effective_iteration(a.iter, a.iter_ctr);
     uint32_t i[D];
-    const bool acc = j < a.ncand && candidate_accepted<D>(a.dims, a.tab, a.seed, a.pid, a.iter, (uint64_t)j, i);
+    const bool acc = j < a.ncand && candidate_accepted<D>(a.dims, a.tab, a.seed, a.pid, iter, (uint64_t)j, i);
     const uint64_t bal = __ballot(acc);
     const int64_t chunk = j / kRejChunk;
-    if ((threadIdx.x & (kWave - 1)) == 0 && chunk < a.nchunks) a.chunk_count[chunk] = (uint32_t)__popcll(bal);
+    const uint32_t cnt = (uint32_t)__popcll(bal);
+    if (a.zstage && acc) {
+        const int64_t o = chunk * kRejChunk + __popcll(bal & ((1ull << lane) - 1ull));
+#pragma unroll
+        for (int k = 0; k < D; ++k) a.zstage[o * D + k] = i[k];
+    }
+    if (lane == 0) {
+        if (chunk < a.nchunks) a.chunk_count[chunk] = cnt;
+        wave_cnt[threadIdx.x / kWave] = cnt;
+    }
+    if (a.group_sum) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t t = 0;
+            for (int w = 0; w < kRejThreads / kWave; ++w) t += wave_cnt[w];
+            a.group_sum[blockIdx.x] = t;
+        }
+    }
 }
 
 // Exclusive scan of the chunk counts by one workgroup of 1024 threads;
@@ -181,8 +221,9 @@ template <int D>
 __global__ __launch_bounds__(kRejThreads) void rej_write_kernel(RejArgs a) {
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t iter = effective_iteration(a.iter, a.iter_ctr);
     uint32_t i[D];
-    const bool acc = j < a.ncand && candidate_accepted<D>(a.dims, a.tab, a.seed, a.pid, a.iter, (uint64_t)j, i);
+    const bool acc = j < a.ncand && candidate_accepted<D>(a.dims, a.tab, a.seed, a.pid, iter, (uint64_t)j, i);
     const uint64_t bal = __ballot(acc);
     const int64_t chunk = j / kRejChunk;
     if (chunk >= a.nchunks) return;  // whole wave beyond the batch
@@ -197,10 +238,11 @@ __global__ __launch_bounds__(kWave) void rej_refill_kernel(RejArgs a) {
     const int lane = threadIdx.x;
     uint64_t filled = a.chunk_prefix[a.nchunks];
     if (filled >= (uint64_t)a.q) return;
+    const uint64_t iter = effective_iteration(a.iter, a.iter_ctr);
     uint64_t base = (uint64_t)a.ncand;
     for (int64_t t = 0; t < kRejMaxRefillTiles * 16 && filled < (uint64_t)a.q; ++t) {
         uint32_t i[D];
-        const bool acc = candidate_accepted<D>(a.dims, a.tab, a.seed, a.pid, a.iter, base + lane, i);
+        const bool acc = candidate_accepted<D>(a.dims, a.tab, a.seed, a.pid, iter, base + lane, i);
         const uint64_t bal = __ballot(acc);
         const uint64_t rank = filled + __popcll(bal & ((1ull << lane) - 1ull));
         if (acc && rank < (uint64_t)a.q) write_zero<D>(a, rank, i);
@@ -219,13 +261,14 @@ static Dims make_dims(const gcp_tensor* X) {
     return d;
 }
 
-static NzTable make_table(const void* table, int64_t slots) {
+static NzTable make_table(const gcp_tensor* X) {
     NzTable t{};
-    if (table && slots > 0) {
-        t.keys = static_cast<const uint64_t*>(table);
-        t.pos = reinterpret_cast<const uint32_t*>(static_cast<const char*>(table) + 8 * slots);
-        t.mask = (uint64_t)slots - 1;
+    if (X->nz_table && X->nz_slots > 0) {
+        t.keys = static_cast<const uint64_t*>(X->nz_table);
+        t.pos = reinterpret_cast<const uint32_t*>(static_cast<const char*>(X->nz_table) + 8 * X->nz_slots);
+        t.mask = (uint64_t)X->nz_slots - 1;
     }
+    t.bitmap = X->nz_bitmap;
     return t;
 }
 
@@ -254,6 +297,20 @@ gcp_status launch_nz_build(const gcp_tensor* X, void* table, int64_t slots, hipS
     return check_launch("gcp_nz_index_build");
 }
 
+gcp_status launch_nz_bitmap(const gcp_tensor* X, uint32_t* bitmap, size_t bytes, hipStream_t s) {
+    const int64_t words = (int64_t)(bytes / 8);  // the size is a whole number of 64-bit words
+    fill_u64_kernel<<<grid_for(words, 256), 256, 0, s>>>(reinterpret_cast<uint64_t*>(bitmap), words, 0ull);
+    if (X->nnz > 0) {
+        const int g = grid_for(X->nnz, 256);
+        const Dims dims = make_dims(X);
+        dispatch_d(X->d, [&](auto dc) {
+            constexpr int D = decltype(dc)::value;
+            hipLaunchKernelGGL(nz_bitmap_kernel<D>, dim3(g), dim3(256), 0, s, X->coo_idx, X->nnz, dims, bitmap);
+        });
+    }
+    return check_launch("gcp_nz_bitmap_build");
+}
+
 template <int D>
 static void direct_launch(const DirectArgs& a, int vdtype, hipStream_t s) {
     const int g = grid_for(a.count, 256);
@@ -270,6 +327,7 @@ gcp_status launch_sample_direct(const gcp_tensor* X, const gcp_sampling* cfg, in
     a.seed = cfg->seed;
     a.pid = cfg->problem_id;
     a.iter = cfg->iteration;
+    a.iter_ctr = cfg->iteration_counter;
     a.kind = kind;
     a.format = X->format;
     a.count = count;
@@ -277,7 +335,7 @@ gcp_status launch_sample_direct(const gcp_tensor* X, const gcp_sampling* cfg, in
     a.nnz = X->nnz;
     a.values = X->values;
     a.coo = X->coo_idx;
-    a.tab = make_table(X->nz_table, X->nz_slots);
+    a.tab = make_table(X);
     a.idx = idx;
     a.xval = xval;
     a.stratum = stratum;
@@ -292,19 +350,22 @@ static RejArgs rej_args(const gcp_tensor* X, const gcp_sampling* cfg, int64_t nc
     a.seed = cfg->seed;
     a.pid = cfg->problem_id;
     a.iter = cfg->iteration;
+    a.iter_ctr = cfg->iteration_counter;
     a.ncand = ncand;
     a.q = cfg->q;
-    a.tab = make_table(X->nz_table, X->nz_slots);
+    a.tab = make_table(X);
     a.vdtype = X->vdtype;
     a.chunk_count = rs.chunk_count;
     a.chunk_prefix = rs.chunk_prefix;
+    a.group_sum = rs.group_sum;
+    a.zstage = rs.zstage;
     a.status = rs.status;
     a.nchunks = rs.nchunks;
     return a;
 }
 
 gcp_status launch_rejection_count(const gcp_tensor* X, const gcp_sampling* cfg, int64_t ncand,
-                                  const RejScratch& rs, hipStream_t s) {
+                                  const RejScratch& rs, bool scan, hipStream_t s) {
     if (cfg->q <= 0) return GCP_OK;
     const RejArgs a = rej_args(X, cfg, ncand, rs);
     const unsigned blocks = (unsigned)((ncand + kRejThreads - 1) / kRejThreads);
@@ -312,7 +373,7 @@ gcp_status launch_rejection_count(const gcp_tensor* X, const gcp_sampling* cfg, 
         constexpr int D = decltype(dc)::value;
         hipLaunchKernelGGL(rej_count_kernel<D>, dim3(blocks), dim3(kRejThreads), 0, s, a);
     });
-    hipLaunchKernelGGL(rej_scan_kernel, dim3(1), dim3(1024), 0, s, a);
+    if (scan) hipLaunchKernelGGL(rej_scan_kernel, dim3(1), dim3(1024), 0, s, a);
     return check_launch("stratified rejection count");
 }
 
@@ -332,6 +393,16 @@ gcp_status launch_rejection_write(const gcp_tensor* X, const gcp_sampling* cfg, 
         hipLaunchKernelGGL(rej_refill_kernel<D>, dim3(1), dim3(kWave), 0, s, a);
     });
     return check_launch("stratified rejection write");
+}
+
+__global__ void bump_counter_kernel(uint64_t* c) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) c[0] += 1;
+}
+
+gcp_status launch_bump_counter(uint64_t* counter, hipStream_t s) {
+    if (!counter) return GCP_OK;
+    hipLaunchKernelGGL(bump_counter_kernel, dim3(1), dim3(64), 0, s, counter);
+    return check_launch("iteration counter");
 }
 
 }  // namespace gcp

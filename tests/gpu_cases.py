@@ -41,7 +41,7 @@ class Problem:
     val64: Optional[np.ndarray]
 
 
-def to_device(w: synth.Workload, vdtype=None, dtype: Optional[str] = None) -> Problem:
+def to_device(w: synth.Workload, vdtype=None, dtype: Optional[str] = None, bitmap: Optional[bool] = None) -> Problem:
     dev = torch.device("cuda:0")
     dtype = dtype or w.dtype
     if vdtype is None:
@@ -54,7 +54,7 @@ def to_device(w: synth.Workload, vdtype=None, dtype: Optional[str] = None) -> Pr
     else:
         ci = torch.as_tensor(np.ascontiguousarray(w.coo_idx).view(np.int32)).to(dev)
         cv = torch.as_tensor(np.asarray(w.coo_val)).to(vdtype).to(dev)
-        X = gcp.coo_tensor(w.dims, ci, cv)
+        X = gcp.coo_tensor(w.dims, ci, cv, bitmap=bitmap)
         dense64 = None
         coo64 = np.asarray(w.coo_idx, dtype=np.int64)
         val64 = torch.as_tensor(np.asarray(w.coo_val)).to(vdtype).to(torch.float64).numpy()

@@ -37,9 +37,9 @@ def test_every_declared_symbol_is_exported():
 
 def test_struct_layouts_match_header():
     m = _lib()
-    assert ctypes.sizeof(m.GcpTensor) == 120
+    assert ctypes.sizeof(m.GcpTensor) == 128
     assert ctypes.sizeof(m.GcpFactors) == 80
-    assert ctypes.sizeof(m.GcpSampling) == 64
+    assert ctypes.sizeof(m.GcpSampling) == 72
 
 
 def test_host_queries():
@@ -51,6 +51,15 @@ def test_host_queries():
     s = L.gcp_nz_table_slots(5_000_000)
     assert s >= 10_000_000 and s & (s - 1) == 0
     assert L.gcp_nz_table_bytes(1 << 21) == 12 << 21
+    t = m.GcpTensor()
+    t.d, t.format = 3, m.COO
+    for k, n in enumerate((1000, 800, 600)):
+        t.dims[k] = n
+    assert L.gcp_nz_bitmap_bytes(ctypes.byref(t)) == 480_000_000 // 8
+    t.dims[2] = 601                                  # 480.8e6 bits -> whole 64-bit words
+    assert L.gcp_nz_bitmap_bytes(ctypes.byref(t)) == -(-480_800_000 // 64) * 8
+    t.format = m.DENSE
+    assert L.gcp_nz_bitmap_bytes(ctypes.byref(t)) == 0
 
 
 def _dense_struct(m, dims, values=0x1000):

@@ -68,21 +68,36 @@ def test_sample_uniform_coo_lookup():
     check_samples(pb, gcp.sample(pb.X, cfg_for(pb, iteration=2)), smp)
 
 
+@pytest.mark.parametrize("membership", ["bitmap", "hash"])
 @pytest.mark.parametrize("p,q", [(2111, 3333), (0, 1025), (1024, 0), (1, 1), (64, 65537)])
-def test_sample_stratified(p, q):
-    announce(f"sample stratified p={p} q={q}")
-    pb = to_device(small_sparse("binary", p=p, q=q))
+def test_sample_stratified(p, q, membership):
+    announce(f"sample stratified p={p} q={q} ({membership})")
+    pb = to_device(small_sparse("binary", p=p, q=q), bitmap=membership == "bitmap")
+    assert (pb.X.nz_bitmap is not None) == (membership == "bitmap")
     for it in (0, 11):
         check_samples(pb, gcp.sample(pb.X, cfg_for(pb, iteration=it)), oracle_samples(pb, iteration=it))
 
 
+@pytest.mark.parametrize("membership", ["bitmap", "hash"])
 @pytest.mark.parametrize("rho", [0.01, 0.5, 1.0, 3.0])
-def test_sample_stratified_refill_independent_of_rho(rho):
-    announce(f"sample stratified rho={rho} (device-side refill)")
+def test_sample_stratified_refill_independent_of_rho(rho, membership):
+    announce(f"sample stratified rho={rho} (device-side refill, {membership})")
     w = small_sparse("binary", dims=(20, 19, 18), p=100, q=5000)
-    pb = to_device(w)
+    pb = to_device(w, bitmap=membership == "bitmap")
     smp = oracle_samples(pb, iteration=4)
     check_samples(pb, gcp.sample(pb.X, cfg_for(pb, iteration=4, rho=rho)), smp)
+
+
+@pytest.mark.parametrize("membership", ["bitmap", "hash"])
+@pytest.mark.parametrize("rho", [0.01, 1.0])
+def test_fused_stratified_refill(rho, membership):
+    announce(f"fused stratified gradient, rho={rho} ({membership})")
+    w = small_sparse("binary", dims=(20, 19, 18), p=700, q=5000)
+    pb = to_device(w, bitmap=membership == "bitmap")
+    G = gcp.sampled_grad(w.loss, pb.X, pb.M, cfg_for(pb, iteration=6, rho=rho))
+    Gref, _, _ = oracle_grad(pb, oracle_samples(pb, iteration=6))
+    torch.cuda.synchronize()
+    assert max(rel_fro(G, Gref)) <= 1e-5
 
 
 def test_sample_stratified_dense_nonzeros():
@@ -270,6 +285,46 @@ def test_sampled_adam_step_matches_two_calls(dtype):
         assert int(adam_a.state[0]) == it + 1 and int(adam_a.state[1]) == 0
         if dtype == "bf16":
             torch.testing.assert_close(pa.M.flat, pa.M.master.to(torch.bfloat16), rtol=0, atol=0)
+
+
+@pytest.mark.parametrize("kind", ["binary", "counts"])
+def test_graph_replay_with_device_iteration_counter(kind):
+    announce(f"hipGraph replay of gcp_sampled_adam_step with a device iteration counter ({kind})")
+    w = small_sparse(kind, rank=8)
+    pa, pb = to_device(w), to_device(w)
+    counter = torch.zeros(1, dtype=torch.int64, device="cuda")
+    cfg_a = gcp.sampling(w.sampler, p=w.p, q=w.q, seed=w.seed, iteration=100, iteration_counter=counter)
+    adam_a = gcp.Adam(pa.M, lr=0.01, lower=0.0)
+    adam_b = gcp.Adam(pb.M, lr=0.01, lower=0.0)
+    step_a = gcp.SampledAdamStep(w.loss, pa.X, pa.M, cfg_a, adam_a, keep_grad=True)
+    step_b = gcp.SampledAdamStep(w.loss, pb.X, pb.M, cfg_for(pb), adam_b, keep_grad=True)
+    step_a()                                   # eager: iteration 100 + 0
+    step_b(iteration=100)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step_a()
+    for rep in range(1, 5):
+        graph.replay()                         # iteration 100 + rep
+        step_b(iteration=100 + rep)
+        torch.cuda.synchronize()
+        assert int(counter.item()) == rep + 1
+        torch.testing.assert_close(step_a.gbuf, step_b.gbuf, rtol=1e-5, atol=1e-6 * float(step_b.gbuf.abs().max()))
+        torch.testing.assert_close(pa.M.flat, pb.M.flat, rtol=1e-5, atol=1e-7)
+        assert int(adam_a.state[0]) == int(adam_b.state[0]) == rep + 1
+        _ = (pa.M.flat * 2).sum().item()        # unrelated eager work between replays
+
+
+def test_sample_iteration_counter():
+    announce("gcp_sample with a device iteration counter")
+    pb = to_device(small_sparse("binary", p=300, q=500))
+    counter = torch.full((1,), 7, dtype=torch.int64, device="cuda")
+    w = pb.w
+    cfg = gcp.sampling(w.sampler, p=w.p, q=w.q, seed=w.seed, iteration=3, iteration_counter=counter)
+    for rep in range(3):
+        got = gcp.sample(pb.X, cfg)
+        check_samples(pb, got, oracle_samples(pb, iteration=3 + 7 + rep))
+        assert int(counter.item()) == 8 + rep
 
 
 # ---------------------------------------------------------------------------
