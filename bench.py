@@ -65,6 +65,34 @@ def algorithmic_bytes(w) -> float:
     return w.p * (per + 4 * d + bv) + w.q * (per + zero_data)
 
 
+KERNEL_SOURCES = ["paper_1906_01687_amd/csrc/grad.hip", "paper_1906_01687_amd/csrc/device.hpp",
+                  "paper_1906_01687_amd/csrc/common.hpp"]
+
+
+def profiled_traffic(workload: str):
+    """HBM bytes per launch of the gradient kernel from the committed PMC summary
+    (FETCH_SIZE + WRITE_SIZE, calibrated on a copy), or None when there is no
+    summary for this workload or the kernel sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"grad_kernel_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("|", "#", " ", "`")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    if "traffic_bytes_per_launch" not in fields or "kernel_source_sha256" not in fields:
+        return None
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != fields["kernel_source_sha256"]:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(w, seconds: float):
     import oracle
     samples, t0, iters = 0, time.perf_counter(), 0
@@ -90,8 +118,9 @@ def cpu_baseline(w, seconds: float):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
-              f"the multi-GPU sharding is described in DESIGN.md and not run.", file=sys.stderr)
+        print(f"bench.py: only single-GPU runs are supported (asked for --gpus {args.gpus}); "
+              f"the sample stream shards by counter range across GPUs, but that path is not built.",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -173,6 +202,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    traffic = profiled_traffic(w.name)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, args.cpu_seconds)
@@ -194,7 +225,8 @@ def main():
                    "loss": ["gaussian", "bernoulli_odds", "poisson"][w.loss], "sampler": sampler_name,
                    "samples_per_step": samples, "p": w.p, "q": w.q, "s": w.s, "parallelism": "single_gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "grad_kernel (fused draws + model + derivative + MTTKRP scatter)",
                      "kernel_us": kernel_ms * 1e3, "algorithmic_bytes_per_launch": balg},
         "cpu_baseline": cpu,

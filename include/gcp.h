@@ -99,7 +99,7 @@ typedef enum gcp_format { GCP_DENSE = 0, GCP_COO = 1 } gcp_format;
  * OUTSIDE is the Kingma-Ba form A <- A - alpha Bhat / (sqrt(Chat) + eps). */
 typedef enum gcp_eps_mode { GCP_EPS_INSIDE_SQRT = 0, GCP_EPS_OUTSIDE_SQRT = 1 } gcp_eps_mode;
 
-/* The data tensor X (Sec. 3.1: dense storage n^d, coordinate storage (d+1) nnz). */
+/* The data tensor X (Sec. 3.2: dense storage n^d, coordinate storage (d+1) nnz). */
 typedef struct gcp_tensor {
     int32_t d;                   /* number of modes, 1..GCP_MAX_D */
     int32_t format;              /* gcp_format */
@@ -280,9 +280,9 @@ gcp_status gcp_adam_step(int64_t P, gcp_dtype dtype, void *A, float *A_master,
  * Kernel timing for measurement harnesses (results never depend on it).
  * gcp_timing_start(n) creates n pairs of HIP events up front (so timing adds
  * no allocation to the calls it measures) and arms them: each following
- * gcp_sampled_grad call records one pair on its stream immediately around
- * its gradient kernel (model entries, derivatives and MTTKRP scatter), until
- * n pairs are used.  Calls on a stream that is being captured into a graph
+ * gcp_sampled_grad / gcp_sampled_adam_step call launches its gradient kernel
+ * (model entries, derivatives and MTTKRP scatter) with one pair stamped at
+ * the kernel's own start and end, until n pairs are used.  Calls on a stream that is being captured into a graph
  * are not timed.  gcp_timing_stop waits for the recorded events, writes the
  * summed kernel time in milliseconds and the number of timed launches, and
  * destroys the events.  Host-global: one timing session at a time. */

@@ -250,23 +250,21 @@ struct Timing {
 };
 static Timing g_timing;
 
-// Records nothing on a stream that is being captured into a graph: an event
-// record there would not give per-replay timings.
-static void timing_record(bool before, hipStream_t s) {
+// The next event pair of an armed timing session, or none.  Nothing is timed
+// on a stream that is being captured into a graph: an event there would not
+// give per-replay timings.
+static void timing_take(hipStream_t s, hipEvent_t* start, hipEvent_t* stop) {
+    *start = *stop = nullptr;
     std::lock_guard<std::mutex> lk(g_timing.mu);
-    if (!g_timing.armed) return;
+    if (!g_timing.armed || g_timing.used >= g_timing.start.size()) return;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
         (void)hipGetLastError();
         return;
     }
-    if (before) {
-        if (g_timing.used < g_timing.start.size() && hipEventRecord(g_timing.start[g_timing.used], s) != hipSuccess)
-            (void)hipGetLastError();
-    } else if (g_timing.used < g_timing.stop.size()) {
-        if (hipEventRecord(g_timing.stop[g_timing.used], s) != hipSuccess) (void)hipGetLastError();
-        ++g_timing.used;
-    }
+    *start = g_timing.start[g_timing.used];
+    *stop = g_timing.stop[g_timing.used];
+    ++g_timing.used;
 }
 
 // The launch sequence shared by gcp_sampled_grad and gcp_sampled_adam_step.
@@ -282,12 +280,12 @@ static gcp_status sampled_common(gcp_loss loss, const gcp_tensor* X, const gcp_f
         if (gcp_status st = launch_rejection_count(X, cfg, f.ncand, f.rs, scanned, stream)) return st;
     }
     if (gcp_status st = launch_fill_zero(f.acc, f.plan.acc_total, stream)) return st;
-    timing_record(true, stream);
-    const gcp_status st = launch_grad_fused(loss, X, M, cfg, eps, f.plan, f.ncand, f.rejection ? &f.rs : nullptr,
-                                            scanned, f.acc, f.partials, loss_sum, adam ? adam->state : nullptr,
-                                            stream);
-    timing_record(false, stream);
-    if (st) return st;
+    hipEvent_t ev0, ev1;
+    timing_take(stream, &ev0, &ev1);
+    if (gcp_status st = launch_grad_fused(loss, X, M, cfg, eps, f.plan, f.ncand, f.rejection ? &f.rs : nullptr,
+                                          scanned, f.acc, f.partials, loss_sum, adam ? adam->state : nullptr, ev0,
+                                          ev1, stream))
+        return st;
     return launch_reduce(M, f.plan, f.acc, f.partials, G, 0, adam, cfg->iteration_counter, stream);
 }
 

@@ -145,12 +145,15 @@ gcp_status launch_grad_list(const gcp_tensor* X, const gcp_factors* M, const uin
                             const void* ytilde, int64_t S, const ScatterPlan& pl, double* acc,
                             void* partials, hipStream_t s);
 
+// ev_start/ev_stop (nullable): events stamped at the kernel's own start and
+// end (launched with hipExtLaunchKernelGGL).
 // adam_state (nullable): the gradient kernel advances the Adam step count
 // state[0] by one; the reduction that follows reads the new value.
 gcp_status launch_grad_fused(gcp_loss loss, const gcp_tensor* X, const gcp_factors* M,
                              const gcp_sampling* cfg, double eps, const ScatterPlan& pl, int64_t ncand,
                              const RejScratch* rs, bool scanned, double* acc, void* partials,
-                             double* loss_sum, int64_t* adam_state, hipStream_t s);
+                             double* loss_sum, int64_t* adam_state, hipEvent_t ev_start, hipEvent_t ev_stop,
+                             hipStream_t s);
 
 // G[k] (nullable entries) from partials and accumulator; with adam != NULL the
 // Adam step is applied to the same elements in the same kernel.

@@ -30,6 +30,7 @@
 // whose global rank is below q -- exactly the first q accepted in counter
 // order.  If the first batch held fewer than q zeros, the wave that owns the
 // last chunk keeps drawing candidates until q are found.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <mutex>
@@ -150,7 +151,10 @@ __device__ __forceinline__ void produce(const GradArgs& a, uint64_t iter, int64_
 // evaluated and scattered.  Every lane of the wave must call this.  Passes
 // are taken kBatch at a time so that the row gathers of a batch are all in
 // flight before any of them is consumed.
-constexpr int kBatch = 4;
+#ifndef GCP_PASS_BATCH
+#define GCP_PASS_BATCH 4
+#endif
+constexpr int kBatch = GCP_PASS_BATCH;
 
 template <int D, typename FT, bool LIST>
 __device__ __forceinline__ void evaluate_and_scatter(const GradArgs& a, double* __restrict__ lds,
@@ -401,10 +405,16 @@ __global__ __launch_bounds__(256) void loss_grad_kernel(LossArgs a) {
 // ---------------------------------------------------------------------------
 constexpr int kRedWaves = 16;
 constexpr int kRedThreads = kRedWaves * kWave;
+#ifndef GCP_REDUCE_UNROLL
+#define GCP_REDUCE_UNROLL 8
+#endif
+#ifndef GCP_REDUCE_PREFETCH
+#define GCP_REDUCE_PREFETCH 1
+#endif
 
 template <typename GT, int ADAM>
-__device__ __forceinline__ void finish_element(const ReduceArgs& a, int k, int64_t local, double g, int64_t t,
-                                               double bc1d, double bc2d) {
+__device__ __forceinline__ void finish_element(const ReduceArgs& a, int k, int64_t local, double g, double bc1d,
+                                               double bc2d, bool have, GT pb, GT pc, GT pa, float pm) {
     const int64_t e = a.off[k] + local;
     void* gk = a.G[0];
 #pragma unroll
@@ -418,31 +428,35 @@ __device__ __forceinline__ void finish_element(const ReduceArgs& a, int k, int64
     }
     if constexpr (ADAM != 0) {
         using T = GT;  // moment type: double for F64 factors, float otherwise
+        T* B = static_cast<T*>(a.B);
+        T* C = static_cast<T*>(a.C);
+        if (!have) {
+            pb = B[e];
+            pc = C[e];
+            if constexpr (ADAM == 2) pm = a.A_master[e];
+            else pa = static_cast<const T*>(a.A)[e];
+        }
         const T gt = (T)g;
         const T b1 = (T)a.beta1, b2 = (T)a.beta2;
         const T omb1 = (T)(1.0 - a.beta1), omb2 = (T)(1.0 - a.beta2);
         const T bc1 = (T)bc1d, bc2 = (T)bc2d;
-        T* B = static_cast<T*>(a.B);
-        T* C = static_cast<T*>(a.C);
-        const T bm = b1 * B[e] + omb1 * gt;
-        const T cm = b2 * C[e] + omb2 * gt * gt;
+        const T bm = b1 * pb + omb1 * gt;
+        const T cm = b2 * pc + omb2 * gt * gt;
         B[e] = bm;
         C[e] = cm;
         const T bhat = bm / bc1, chat = cm / bc2;
         const T den = a.eps_mode == GCP_EPS_INSIDE_SQRT ? sqrt(chat + (T)a.eps) : sqrt(chat) + (T)a.eps;
         const T step = (T)a.alpha * bhat / den;
         if constexpr (ADAM == 2) {
-            float v = a.A_master[e] - (float)step;
+            float v = pm - (float)step;
             v = v < (float)a.lower ? (float)a.lower : v;
             a.A_master[e] = v;
             static_cast<bf16_t*>(a.A)[e] = to_bf16(v);
         } else {
-            T* A = static_cast<T*>(a.A);
-            T v = A[e] - step;
-            A[e] = v < (T)a.lower ? (T)a.lower : v;
+            T v = pa - step;
+            static_cast<T*>(a.A)[e] = v < (T)a.lower ? (T)a.lower : v;
         }
     }
-    (void)t;
 }
 
 template <typename GT, int ADAM>
@@ -470,26 +484,41 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(ReduceArgs a) {
     if (priv) {
         const int64_t local = lb * kWave + lane;
         const bool in = local < nk;
+        // wave 0 fetches the Adam operands of its elements before the partials,
+        // so their latency overlaps the partial reads
+        GT pb = GT(0), pc = GT(0), pa = GT(0);
+        float pm = 0.f;
+        if (ADAM && GCP_REDUCE_PREFETCH && wv == 0 && in) {
+            const int64_t e = a.off[k] + local;
+            pb = static_cast<const GT*>(a.B)[e];
+            pc = static_cast<const GT*>(a.C)[e];
+            if constexpr (ADAM == 2) pm = a.A_master[e];
+            else pa = static_cast<const GT*>(a.A)[e];
+        }
         double s = 0.0;
         if (in) {
-            // eight independent partial sums keep eight loads in flight; they are
-            // combined in a fixed order, so the result does not depend on timing
+            // sixteen independent partial sums keep sixteen loads in flight; they
+            // are combined in a fixed order, so the result does not depend on timing
             const int64_t pe = a.lds_off[k] + local;
             const GT* __restrict__ parts = static_cast<const GT*>(a.partials);  // partial type = gradient type
-            constexpr int U = 8;
-            double acc8[U];
+            constexpr int U = GCP_REDUCE_UNROLL;
+            double acc16[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) acc8[u] = 0.0;
+            for (int u = 0; u < U; ++u) acc16[u] = 0.0;
             int64_t b = wv;
             for (; b + (U - 1) * kRedWaves < a.nparts; b += U * kRedWaves) {
                 GT v[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) v[u] = parts[(b + u * kRedWaves) * a.lds_total + pe];
 #pragma unroll
-                for (int u = 0; u < U; ++u) acc8[u] += (double)v[u];
+                for (int u = 0; u < U; ++u) acc16[u] += (double)v[u];
             }
-            for (; b < a.nparts; b += kRedWaves) acc8[0] += (double)parts[b * a.lds_total + pe];
-            s = ((acc8[0] + acc8[1]) + (acc8[2] + acc8[3])) + ((acc8[4] + acc8[5]) + (acc8[6] + acc8[7]));
+            for (; b < a.nparts; b += kRedWaves) acc16[0] += (double)parts[b * a.lds_total + pe];
+#pragma unroll
+            for (int w = U / 2; w > 0; w >>= 1)
+#pragma unroll
+                for (int u = 0; u < w; ++u) acc16[u] += acc16[u + w];
+            s = acc16[0];
         }
         wave_sum[wv][lane] = s;
         __syncthreads();
@@ -497,15 +526,15 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(ReduceArgs a) {
             double g = 0.0;
 #pragma unroll
             for (int w = 0; w < kRedWaves; ++w) g += wave_sum[w][lane];
-            finish_element<GT, ADAM>(a, k, local, g, ADAM ? t_shared : 0, ADAM ? bc_shared[0] : 1.0,
-                                     ADAM ? bc_shared[1] : 1.0);
+            finish_element<GT, ADAM>(a, k, local, g, ADAM ? bc_shared[0] : 1.0, ADAM ? bc_shared[1] : 1.0,
+                                     GCP_REDUCE_PREFETCH != 0, pb, pc, pa, pm);
         }
     } else {
         __syncthreads();
         const int64_t local = lb * kRedThreads + threadIdx.x;
         if (local < nk)
-            finish_element<GT, ADAM>(a, k, local, a.acc[a.acc_off[k] + local], ADAM ? t_shared : 0,
-                                     ADAM ? bc_shared[0] : 1.0, ADAM ? bc_shared[1] : 1.0);
+            finish_element<GT, ADAM>(a, k, local, a.acc[a.acc_off[k] + local], ADAM ? bc_shared[0] : 1.0,
+                                     ADAM ? bc_shared[1] : 1.0, false, GT(0), GT(0), GT(0), 0.f);
     }
 }
 
@@ -607,12 +636,16 @@ size_t scatter_partials_bytes(const ScatterPlan& pl, int fdtype) {
 }
 
 template <int D, bool LIST>
-static void grad_launch(const GradArgs& a, const ScatterPlan& pl, int fdtype, int vdtype, hipStream_t s) {
+static void grad_launch(const GradArgs& a, const ScatterPlan& pl, int fdtype, int vdtype, hipStream_t s,
+                        hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr) {
     const dim3 g((unsigned)pl.blocks), b((unsigned)pl.threads);
     const size_t shm = (size_t)pl.lds_total * 8;
     auto go = [&](auto kernel) {
         allow_full_lds(reinterpret_cast<const void*>(kernel));
-        hipLaunchKernelGGL(kernel, g, b, shm, s, a);
+        if (ev_start || ev_stop)
+            hipExtLaunchKernelGGL(kernel, g, b, (std::uint32_t)shm, s, ev_start, ev_stop, 0u, a);
+        else
+            hipLaunchKernelGGL(kernel, g, b, shm, s, a);
     };
     if (fdtype == GCP_F64) {
         if (vdtype == GCP_F64) go(grad_kernel<D, double, double, LIST>);
@@ -675,7 +708,7 @@ int64_t fused_items(const gcp_sampling* cfg, int64_t ncand) {
 gcp_status launch_grad_fused(gcp_loss loss, const gcp_tensor* X, const gcp_factors* M, const gcp_sampling* cfg,
                              double eps, const ScatterPlan& pl, int64_t ncand, const RejScratch* rs,
                              bool scanned, double* acc, void* partials, double* loss_sum, int64_t* adam_state,
-                             hipStream_t s) {
+                             hipEvent_t ev_start, hipEvent_t ev_stop, hipStream_t s) {
     GradArgs a = base_args(X, M, pl, acc, partials);
     a.loss = loss;
     a.sampler = cfg->sampler;
@@ -709,7 +742,9 @@ gcp_status launch_grad_fused(gcp_loss loss, const gcp_tensor* X, const gcp_facto
     }
     a.n_direct_items = (a.n_direct + kWave - 1) / kWave;
     // with nothing sampled the single workgroup still publishes a zero partial
-    dispatch_d(X->d, [&](auto dc) { grad_launch<decltype(dc)::value, false>(a, pl, M->dtype, X->vdtype, s); });
+    dispatch_d(X->d, [&](auto dc) {
+        grad_launch<decltype(dc)::value, false>(a, pl, M->dtype, X->vdtype, s, ev_start, ev_stop);
+    });
     return check_launch("gcp_sampled_grad");
 }
 
