@@ -277,12 +277,91 @@ gcp_status gcp_adam_step(int64_t P, gcp_dtype dtype, void *A, float *A_master,
                          double lower, gcp_eps_mode eps_mode, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Batches of independent problems: one persistent gradient launch and one
+ * reduction + Adam launch advance every problem of the batch by one step of
+ * Alg. 4's inner loop.  The persistent workgroups share the batch's samples
+ * by estimated cost (gcp_batch_schedule), so problems of very different sizes
+ * finish together.
+ *
+ * gcp_problem describes one problem: its data X, factors M (M.A[k] must be
+ * the mode-k blocks of the flat array A), sampling cfg (UNIFORM or
+ * SEMI_STRATIFIED; cfg.iteration is the problem's base iteration and
+ * cfg.iteration_counter is ignored -- the batch call takes one counter for
+ * all problems), loss and its eps, the Adam projection bound `lower`, and the
+ * flat parameter, moment and (nullable) gradient arrays.  All problems of a
+ * batch share d, the factor dtype and the value dtype.  Each problem's
+ * samples are exactly those gcp_sample would draw for it alone (its own seed
+ * and problem_id), so a batch and per-problem calls agree up to floating-point
+ * order.
+ *
+ * gcp_batched_create plans the batch on the host (no device work) and
+ * returns an opaque handle; gcp_batched_workspace_bytes sizes its workspace;
+ * gcp_batched_prepare uploads the descriptor tables into the workspace and
+ * clears the gradient accumulators (set-up, synchronises the stream);
+ * gcp_batched_grad writes every problem's G; gcp_batched_adam_step applies
+ * Adam to every problem (state as in gcp_adam_step, one for the batch).  Both
+ * step calls are asynchronous, launch two kernels and can be captured in a
+ * HIP graph; they leave the accumulators cleared.  Calls on one batch must not
+ * overlap.  `tune` (nullable) sets the launch shape; zeros pick defaults. */
+typedef struct gcp_problem {
+    gcp_tensor X;
+    gcp_factors M;
+    gcp_sampling cfg;
+    int32_t loss;                /* gcp_loss */
+    int32_t reserved;            /* set to 0 */
+    double eps;                  /* loss eps (1e-10 in the examples) */
+    double lower;                /* Adam projection bound; -INFINITY for none */
+    void *A;                     /* flat parameters, sum_k n_k r values of M.dtype */
+    float *A_master;             /* GCP_BF16 only: float master copy */
+    void *B;                     /* Adam moments (FP64 for FP64 factors, else FP32) */
+    void *C;
+    void *G;                     /* nullable: flat gradient output */
+} gcp_problem;
+
+typedef enum gcp_batch_schedule {
+    /* every workgroup takes one run of the problem-ordered 64-sample items of
+       equal estimated cost: a problem spans few workgroups, so few LDS
+       partials are flushed per step */
+    GCP_BATCH_CONTIGUOUS = 0,
+    /* work units of unit_items items, dealt largest first to the least-loaded
+       workgroup (longest-processing-time scheduling) */
+    GCP_BATCH_LPT = 1
+} gcp_batch_schedule;
+
+typedef struct gcp_batch_tuning {
+    int32_t threads;             /* threads per gradient workgroup: 256, 512 or 1024 (0: 1024) */
+    int32_t unit_items;          /* GCP_BATCH_LPT: 64-sample items per work unit (0: 64) */
+    int32_t schedule;            /* gcp_batch_schedule */
+    int32_t reserved;
+} gcp_batch_tuning;
+
+typedef struct gcp_batch gcp_batch;
+
+gcp_status gcp_batched_create(const gcp_problem *problems, int32_t count,
+                              const gcp_batch_tuning *tune, gcp_batch **batch);
+size_t gcp_batched_workspace_bytes(const gcp_batch *batch);
+gcp_status gcp_batched_prepare(gcp_batch *batch, void *ws, size_t ws_bytes, hipStream_t stream);
+gcp_status gcp_batched_grad(gcp_batch *batch, uint64_t *iteration_counter, hipStream_t stream);
+gcp_status gcp_batched_adam_step(gcp_batch *batch, int64_t *state, uint64_t *iteration_counter,
+                                 double alpha, double beta1, double beta2, double adam_eps,
+                                 gcp_eps_mode eps_mode, hipStream_t stream);
+/* The host plan of a batch (no device work): the number of gradient
+ * workgroups and work units; then, for arrays that are non-NULL, the first
+ * unit of every workgroup (block_ptr, n_blocks + 1 entries, caller-owned),
+ * each unit's problem (n_units entries) and its half-open range of 64-sample
+ * items (unit_items, 2 * n_units entries: begin, end).  Call once with NULL
+ * arrays to size them. */
+gcp_status gcp_batched_plan(const gcp_batch *batch, int64_t *n_blocks, int64_t *n_units,
+                            int64_t *block_ptr, int32_t *unit_problem, int64_t *unit_items);
+void gcp_batched_destroy(gcp_batch *batch);
+
+/* ---------------------------------------------------------------------------
  * Kernel timing for measurement harnesses (results never depend on it).
  * gcp_timing_start(n) creates n pairs of HIP events up front (so timing adds
  * no allocation to the calls it measures) and arms them: each following
- * gcp_sampled_grad / gcp_sampled_adam_step call launches its gradient kernel
- * (model entries, derivatives and MTTKRP scatter) with one pair stamped at
- * the kernel's own start and end, until n pairs are used.  Calls on a stream that is being captured into a graph
+ * gcp_sampled_grad / gcp_sampled_adam_step / gcp_batched_* step call launches
+ * its gradient kernel (model entries, derivatives and MTTKRP scatter) with one
+ * pair stamped at the kernel's own start and end, until n pairs are used.  Calls on a stream that is being captured into a graph
  * are not timed.  gcp_timing_stop waits for the recorded events, writes the
  * summed kernel time in milliseconds and the number of timed launches, and
  * destroys the events.  Host-global: one timing session at a time. */

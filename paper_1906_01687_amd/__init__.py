@@ -2,8 +2,10 @@
 Large-Scale Tensor Decomposition): hand-written HIP kernels for gfx950 behind
 the C ABI in include/gcp.h, with a thin torch binding in ``api``."""
 from . import _lib
-from .api import (Adam, DataTensor, Factors, LOSSES, SAMPLERS, SampledAdamStep, SampledGrad, coo_tensor,
-                  dense_tensor, loss_grad, mttkrp, n_samples, sample, sampled_grad, sampling)
+from ._lib import BATCH_CONTIGUOUS, BATCH_LPT
+from .api import (Adam, Batch, DataTensor, Factors, LOSSES, Problem, SAMPLERS, SampledAdamStep, SampledGrad,
+                  coo_tensor, dense_tensor, loss_grad, mttkrp, n_samples, sample, sampled_grad, sampling)
 
-__all__ = ["Adam", "DataTensor", "Factors", "LOSSES", "SAMPLERS", "SampledAdamStep", "SampledGrad", "coo_tensor",
-           "dense_tensor", "loss_grad", "mttkrp", "n_samples", "sample", "sampled_grad", "sampling"]
+__all__ = ["BATCH_CONTIGUOUS", "BATCH_LPT", "Adam", "Batch", "DataTensor", "Factors", "LOSSES", "Problem", "SAMPLERS", "SampledAdamStep",
+           "SampledGrad", "coo_tensor", "dense_tensor", "loss_grad", "mttkrp", "n_samples", "sample",
+           "sampled_grad", "sampling"]

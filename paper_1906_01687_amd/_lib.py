@@ -51,12 +51,28 @@ class GcpSampling(ctypes.Structure):
                 ("iteration_counter", ctypes.c_void_p)]
 
 
+class GcpProblem(ctypes.Structure):
+    _fields_ = [("X", GcpTensor), ("M", GcpFactors), ("cfg", GcpSampling), ("loss", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("eps", ctypes.c_double), ("lower", ctypes.c_double),
+                ("A", ctypes.c_void_p), ("A_master", ctypes.c_void_p), ("B", ctypes.c_void_p),
+                ("C", ctypes.c_void_p), ("G", ctypes.c_void_p)]
+
+
+class GcpBatchTuning(ctypes.Structure):
+    _fields_ = [("threads", ctypes.c_int32), ("unit_items", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+BATCH_CONTIGUOUS, BATCH_LPT = 0, 1
+
+
 EXPORTS = [
     "gcp_last_error", "gcp_abi_version", "gcp_nz_table_slots", "gcp_nz_table_bytes",
     "gcp_nz_index_build", "gcp_nz_bitmap_bytes", "gcp_nz_bitmap_build", "gcp_sample_workspace_bytes", "gcp_sample", "gcp_loss_grad",
     "gcp_mttkrp_workspace_bytes", "gcp_mttkrp", "gcp_sampled_grad_workspace_bytes",
     "gcp_sampled_grad", "gcp_sampled_adam_step", "gcp_adam_step", "gcp_timing_start",
-    "gcp_timing_stop",
+    "gcp_timing_stop", "gcp_batched_create", "gcp_batched_workspace_bytes", "gcp_batched_prepare", "gcp_batched_plan",
+    "gcp_batched_grad", "gcp_batched_adam_step", "gcp_batched_destroy",
 ]
 
 _lib = None
@@ -92,6 +108,14 @@ def lib() -> ctypes.CDLL:
                                        ctypes.c_int, P, P, P, sz, P]),
         "gcp_adam_step": (st, [i64, ctypes.c_int, P, P, P, P, P, P, dbl, dbl, dbl, dbl, dbl,
                                ctypes.c_int, P]),
+        "gcp_batched_create": (st, [ctypes.POINTER(GcpProblem), ctypes.c_int32, ctypes.POINTER(GcpBatchTuning),
+                                    ctypes.POINTER(ctypes.c_void_p)]),
+        "gcp_batched_workspace_bytes": (sz, [P]),
+        "gcp_batched_prepare": (st, [P, P, sz, P]),
+        "gcp_batched_grad": (st, [P, P, P]),
+        "gcp_batched_adam_step": (st, [P, P, P, dbl, dbl, dbl, dbl, ctypes.c_int, P]),
+        "gcp_batched_plan": (st, [P, P, P, P, P, P]),
+        "gcp_batched_destroy": (None, [P]),
         "gcp_timing_start": (st, [i64]),
         "gcp_timing_stop": (st, [ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
     }

@@ -339,3 +339,93 @@ class Adam:
                                   _ptr(self.B), _ptr(self.C), _ptr(self.state), float(self.lr),
                                   float(self.beta1), float(self.beta2), float(self.eps), float(self.lower),
                                   int(self.eps_mode), _stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# batches of independent problems (gcp_batched_*)
+# ---------------------------------------------------------------------------
+
+class Problem:
+    """One problem of a batch: data, factors, sampling, loss and Adam buffers."""
+
+    def __init__(self, loss, X: DataTensor, M: Factors, cfg: GcpSampling, eps: float = LOSS_EPS,
+                 lower: float = -math.inf, keep_grad: bool = False):
+        self.loss = _loss_code(loss)
+        self.X, self.M, self.cfg = X, M, cfg
+        self.eps, self.lower = float(eps), float(lower)
+        mdt = torch.float64 if M.dtype == torch.float64 else torch.float32
+        dev = M.flat.device
+        self.B = torch.zeros(M.P, dtype=mdt, device=dev)
+        self.C = torch.zeros(M.P, dtype=mdt, device=dev)
+        self.G = torch.zeros(M.P, dtype=mdt, device=dev) if keep_grad else None
+
+    def struct(self, with_grad: bool = True) -> _lib.GcpProblem:
+        pr = _lib.GcpProblem()
+        pr.X = self.X.struct()
+        pr.M = self.M.struct()
+        pr.cfg = self.cfg
+        pr.loss = self.loss
+        pr.eps = self.eps
+        pr.lower = self.lower
+        pr.A = _ptr(self.M.flat)
+        pr.A_master = _ptr(self.M.master)
+        pr.B = _ptr(self.B)
+        pr.C = _ptr(self.C)
+        pr.G = _ptr(self.G) if with_grad else None
+        return pr
+
+
+class Batch:
+    """A planned and prepared batch: one gradient launch and one reduction (+ Adam)
+    advance every problem.  ``tune`` = (threads, unit_items[, schedule]) or None
+    for defaults; schedule is BATCH_CONTIGUOUS (default) or BATCH_LPT."""
+
+    def __init__(self, problems: Sequence[Problem], tune=None, with_grad: bool = True):
+        L = lib()
+        self.problems = list(problems)
+        arr = (_lib.GcpProblem * len(self.problems))(*[p.struct(with_grad) for p in self.problems])
+        t = _lib.GcpBatchTuning()
+        if tune is not None:
+            t.threads, t.unit_items = int(tune[0]), int(tune[1])
+            t.schedule = int(tune[2]) if len(tune) > 2 else _lib.BATCH_CONTIGUOUS
+        self.tune = tune
+        h = ctypes.c_void_p()
+        check(L.gcp_batched_create(arr, len(self.problems), ctypes.byref(t), ctypes.byref(h)))
+        self.handle = h
+        dev = self.problems[0].M.flat.device
+        self.nbytes = int(L.gcp_batched_workspace_bytes(h))
+        self.ws = torch.empty(max(self.nbytes, 1), dtype=torch.uint8, device=dev)
+        check(L.gcp_batched_prepare(h, _ptr(self.ws), self.nbytes, _stream(None)))
+        self.state = torch.zeros(2, dtype=torch.int64, device=dev)
+        self.counter = torch.zeros(1, dtype=torch.int64, device=dev)
+
+    def plan(self):
+        """The host plan: (block_ptr, unit_problem, unit_items[n_units, 2]) as numpy arrays."""
+        import numpy as np
+        L = lib()
+        nb, nu = ctypes.c_int64(), ctypes.c_int64()
+        check(L.gcp_batched_plan(self.handle, ctypes.byref(nb), ctypes.byref(nu), None, None, None))
+        bp = np.zeros(nb.value + 1, dtype=np.int64)
+        up = np.zeros(max(1, nu.value), dtype=np.int32)
+        ui = np.zeros((max(1, nu.value), 2), dtype=np.int64)
+        check(L.gcp_batched_plan(self.handle, None, None, bp.ctypes.data, up.ctypes.data, ui.ctypes.data))
+        return bp, up[:nu.value], ui[:nu.value]
+
+    def grad(self, stream=None) -> None:
+        check(lib().gcp_batched_grad(self.handle, _ptr(self.counter), _stream(stream)))
+
+    def adam_step(self, lr: float = 0.01, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
+                  eps_mode: int = _lib.EPS_INSIDE_SQRT, stream=None) -> None:
+        check(lib().gcp_batched_adam_step(self.handle, _ptr(self.state), _ptr(self.counter), float(lr),
+                                          float(beta1), float(beta2), float(eps), int(eps_mode), _stream(stream)))
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().gcp_batched_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

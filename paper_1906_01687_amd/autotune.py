@@ -1,0 +1,96 @@
+"""Launch-shape autotuner for batches (gcp_batched_*).
+
+The tunables are the gradient workgroup size (256, 512 or 1024 threads), the
+schedule (one contiguous run of items per workgroup, or longest-processing-
+time dealing of units) and, for the latter, the work-unit size (64-sample
+items per unit: small units balance load across workgroups, large ones let a
+workgroup hold more of one problem, so fewer LDS partials are flushed).  Each candidate is planned and prepared as a separate batch whose
+problems publish no gradient and take no Adam step, timed over a few
+gradient-only steps with the library's dispatch-stamped kernel events, and the
+fastest is kept.  Results are cached in a JSON file keyed by the batch's shape
+signature (dims, ranks, losses, samplers, sample counts, dtypes, device).
+"""
+from __future__ import annotations
+
+import ctypes
+import hashlib
+import json
+import os
+import sys
+from typing import Dict, Iterable, Optional, Sequence, Tuple
+
+import torch
+
+from . import _lib
+from .api import Batch, Problem
+
+DEFAULT_CANDIDATES: Tuple[Tuple[int, int, int], ...] = tuple(
+    [(t, 0, _lib.BATCH_CONTIGUOUS) for t in (256, 512, 1024)]
+    + [(t, u, _lib.BATCH_LPT) for t in (256, 512, 1024) for u in (16, 64, 256)])
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "gcp_mi355x", "batch_tuning.json")
+
+
+def signature(problems: Sequence[Problem]) -> str:
+    h = hashlib.sha256()
+    dev = problems[0].M.flat.device
+    h.update(torch.cuda.get_device_properties(dev).gcnArchName.encode())
+    for p in problems:
+        c = p.cfg
+        h.update(repr((p.X.dims, p.M.rank, str(p.M.dtype), str(p.X.values.dtype), p.X.is_dense, p.loss,
+                       c.sampler, c.s, c.p, c.q)).encode())
+    return h.hexdigest()[:32]
+
+
+def _time_candidate(problems: Sequence[Problem], tune, steps: int, warmup: int) -> float:
+    L = _lib.lib()
+    batch = Batch(problems, tune=tune, with_grad=False)
+    try:
+        for _ in range(warmup):
+            batch.grad()
+        torch.cuda.synchronize()
+        _lib.check(L.gcp_timing_start(steps))
+        for _ in range(steps):
+            batch.grad()
+        torch.cuda.synchronize()
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _lib.check(L.gcp_timing_stop(ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value / max(1, n.value)
+    finally:
+        batch.close()
+
+
+def tune_batch(problems: Sequence[Problem], candidates: Optional[Iterable[Tuple[int, ...]]] = None,
+               steps: int = 10, warmup: int = 2, cache_path: Optional[str] = DEFAULT_CACHE,
+               verbose: bool = False) -> Tuple[Tuple[int, ...], Dict[str, float]]:
+    """Best (threads, unit_items, schedule) for this batch and the timings (ms)
+    of all candidates; a cached answer for the same signature is returned
+    untimed."""
+    sig = signature(problems)
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        try:
+            with open(cache_path) as fh:
+                cache = json.load(fh)
+        except (OSError, ValueError):
+            cache = {}
+    if sig in cache:
+        entry = cache[sig]
+        return tuple(entry["best"]), entry.get("times", {})
+    times: Dict[str, float] = {}
+    best, best_ms = None, float("inf")
+    for tune in (candidates or DEFAULT_CANDIDATES):
+        ms = _time_candidate(problems, tune, steps, warmup)
+        times["x".join(str(v) for v in tune)] = ms
+        if verbose:
+            print(f"[autotune] threads={tune[0]} unit_items={tune[1]} schedule={tune[2] if len(tune) > 2 else 0}: "
+                  f"{ms * 1e3:.1f} us", file=sys.stderr, flush=True)
+        if ms < best_ms:
+            best, best_ms = tuple(tune), ms
+    if cache_path:
+        cache[sig] = {"best": list(best), "times": times}
+        os.makedirs(os.path.dirname(cache_path), exist_ok=True)
+        tmp = cache_path + f".tmp{os.getpid()}"
+        with open(tmp, "w") as fh:
+            json.dump(cache, fh, indent=1)
+        os.replace(tmp, cache_path)
+    return best, times

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libgcp.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["abi.cpp", "sample.hip", "grad.hip", "adam.hip"]
+SOURCES = ["abi.cpp", "sample.hip", "grad.hip", "adam.hip", "batched.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -17,6 +17,8 @@ namespace gcp {
 
 static thread_local std::string g_last_error;
 
+static std::string gcp_last_error_str() { return g_last_error; }
+
 gcp_status set_error(gcp_status st, const std::string& msg) {
     g_last_error = msg;
     return st;
@@ -289,6 +291,30 @@ static gcp_status sampled_common(gcp_loss loss, const gcp_tensor* X, const gcp_f
     return launch_reduce(M, f.plan, f.acc, f.partials, G, 0, adam, cfg->iteration_counter, stream);
 }
 
+// One problem of a batch (gcp_batched_create).
+static gcp_status check_problem(const gcp_problem* pr, int32_t b) {
+    const std::string at = "problem " + std::to_string(b) + ": ";
+    if (gcp_status st = check_loss((gcp_loss)pr->loss)) return set_error(st, at + gcp_last_error_str());
+    if (gcp_status st = check_tensor(&pr->X)) return set_error(st, at + gcp_last_error_str());
+    if (gcp_status st = check_sampling(&pr->X, &pr->cfg)) return set_error(st, at + gcp_last_error_str());
+    if (pr->cfg.sampler == GCP_SAMPLER_STRATIFIED)
+        return set_error(GCP_ERR_UNSUPPORTED, at + "batches take UNIFORM or SEMI_STRATIFIED sampling");
+    if (gcp_status st = check_factors(&pr->X, &pr->M)) return set_error(st, at + gcp_last_error_str());
+    int64_t P = 0;
+    for (int k = 0; k < pr->X.d; ++k) P += pr->X.dims[k] * pr->M.rank;
+    if (P > 0 && (!pr->A || !pr->B || !pr->C)) return set_error(GCP_ERR_INVALID_ARG, at + "A, B and C must be non-NULL");
+    if (pr->M.dtype == GCP_BF16 && !pr->A_master)
+        return set_error(GCP_ERR_INVALID_ARG, at + "GCP_BF16 needs the float master copy A_master");
+    const size_t esz = pr->M.dtype == GCP_F64 ? 8 : (pr->M.dtype == GCP_F32 ? 4 : 2);
+    int64_t off = 0;
+    for (int k = 0; k < pr->X.d; ++k) {
+        if (pr->M.A[k] != static_cast<const char*>(pr->A) + off * esz)
+            return set_error(GCP_ERR_INVALID_ARG, at + "M.A[k] must be the mode-k block of the flat array A");
+        off += pr->X.dims[k] * pr->M.rank;
+    }
+    return GCP_OK;
+}
+
 }  // namespace gcp
 
 using namespace gcp;
@@ -471,6 +497,50 @@ gcp_status gcp_adam_step(int64_t P, gcp_dtype dtype, void* A, float* A_master, c
     if (P > 0 && !G) return set_error(GCP_ERR_INVALID_ARG, "G must be non-NULL");
     return launch_adam(P, dtype, A, A_master, G, B, C, state, alpha, beta1, beta2, eps, lower, eps_mode, stream);
 }
+
+gcp_status gcp_batched_create(const gcp_problem* problems, int32_t count, const gcp_batch_tuning* tune,
+                              gcp_batch** batch) {
+    clear_error();
+    return batch_create(problems, count, tune, batch, check_problem);
+}
+
+size_t gcp_batched_workspace_bytes(const gcp_batch* batch) { return batch_ws_bytes(batch); }
+
+gcp_status gcp_batched_prepare(gcp_batch* batch, void* ws, size_t ws_bytes, hipStream_t stream) {
+    clear_error();
+    return batch_prepare(batch, ws, ws_bytes, stream);
+}
+
+gcp_status gcp_batched_grad(gcp_batch* batch, uint64_t* iteration_counter, hipStream_t stream) {
+    clear_error();
+    hipEvent_t ev0, ev1;
+    timing_take(stream, &ev0, &ev1);
+    return batch_step(batch, nullptr, iteration_counter, ev0, ev1, stream);
+}
+
+gcp_status gcp_batched_adam_step(gcp_batch* batch, int64_t* state, uint64_t* iteration_counter, double alpha,
+                                 double beta1, double beta2, double adam_eps, gcp_eps_mode eps_mode,
+                                 hipStream_t stream) {
+    clear_error();
+    if (!state) return set_error(GCP_ERR_INVALID_ARG, "state is NULL");
+    if (eps_mode != GCP_EPS_INSIDE_SQRT && eps_mode != GCP_EPS_OUTSIDE_SQRT)
+        return set_error(GCP_ERR_INVALID_ARG, "eps_mode is not a gcp_eps_mode");
+    if (!(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0))
+        return set_error(GCP_ERR_INVALID_ARG, "beta1 and beta2 must be in [0, 1)");
+    if (!(adam_eps >= 0.0) || !(alpha >= 0.0)) return set_error(GCP_ERR_INVALID_ARG, "alpha and eps must be >= 0");
+    const AdamParams ap{nullptr, nullptr, nullptr, nullptr, state, alpha, beta1, beta2, adam_eps, 0.0, (int)eps_mode};
+    hipEvent_t ev0, ev1;
+    timing_take(stream, &ev0, &ev1);
+    return batch_step(batch, &ap, iteration_counter, ev0, ev1, stream);
+}
+
+gcp_status gcp_batched_plan(const gcp_batch* batch, int64_t* n_blocks, int64_t* n_units, int64_t* block_ptr,
+                            int32_t* unit_problem, int64_t* unit_items) {
+    clear_error();
+    return batch_plan(batch, n_blocks, n_units, block_ptr, unit_problem, unit_items);
+}
+
+void gcp_batched_destroy(gcp_batch* batch) { batch_destroy(batch); }
 
 gcp_status gcp_timing_start(int64_t max_launches) {
     clear_error();

@@ -162,6 +162,18 @@ gcp_status launch_reduce(const gcp_factors* M, const ScatterPlan& pl, const doub
                          const void* partials, void* const* G, int accumulate, const AdamParams* adam,
                          uint64_t* bump_counter, hipStream_t s);
 
+// Batched problems (batched.hip); check_problem validates one problem.
+gcp_status batch_create(const gcp_problem* problems, int32_t count, const gcp_batch_tuning* tune, gcp_batch** out,
+                        gcp_status (*check_problem)(const gcp_problem*, int32_t));
+size_t batch_ws_bytes(const gcp_batch* b);
+gcp_status batch_prepare(gcp_batch* b, void* ws, size_t ws_bytes, hipStream_t s);
+gcp_status batch_step(gcp_batch* b, const AdamParams* adam, uint64_t* iteration_counter, hipEvent_t e0, hipEvent_t e1,
+                      hipStream_t s);
+void batch_destroy(gcp_batch* b);
+int64_t batch_blocks(const gcp_batch* b);
+gcp_status batch_plan(const gcp_batch* b, int64_t* n_blocks, int64_t* n_units, int64_t* block_ptr,
+                      int32_t* unit_problem, int64_t* unit_items);
+
 gcp_status launch_adam(int64_t P, gcp_dtype dtype, void* A, float* A_master, const void* G,
                        void* B, void* C, int64_t* state, double alpha, double beta1, double beta2,
                        double eps, double lower, gcp_eps_mode eps_mode, hipStream_t s);

@@ -119,7 +119,7 @@ def _subsample_models(A, count, rng):
     return prod.sum(axis=1)
 
 
-def _bisect_scale(target, func, lo=1e-12, hi=1e12, iters=200):
+def _bisect_scale(target, func, lo=1e-12, hi=1e12, iters=80):
     """Scale lambda (geometric bisection) with func(lambda) = target, func increasing."""
     for _ in range(iters):
         mid = np.sqrt(lo * hi)
@@ -253,7 +253,7 @@ def sparse_binary_workload(dims=(1000, 800, 600), rank=8, density=0.002, p=100_0
             out[f"A{k}"] = a
         return out
 
-    key = f"sparse_binary:{dims}:{rank}:{density}:{seed_base}:v2"
+    key = f"sparse_binary:{dims}:{rank}:{density}:{seed_base}:v3"
     z = _cached(key, make) if cache else make()
     A_true = [z[f"A{k}"] for k in range(d)]
     A0 = nonneg_start(dims, rank, seed_base + 2, "uniform", float(z["scale"]))
@@ -273,7 +273,7 @@ def sparse_count_workload(dims=(6000, 24, 77, 32), rank=10, nnz_target=5.0e6, p=
             out[f"A{k}"] = a
         return out
 
-    key = f"sparse_counts:{dims}:{rank}:{nnz_target}:{seed_base}:v2"
+    key = f"sparse_counts:{dims}:{rank}:{nnz_target}:{seed_base}:v3"
     z = _cached(key, make) if cache else make()
     A_true = [z[f"A{k}"] for k in range(d)]
     A0 = nonneg_start(dims, rank, seed_base + 2, "gamma", float(z["scale"]))
@@ -295,3 +295,71 @@ WORKLOADS = {
     "sparse_binary_1000x800x600": sparse_binary_1000x800x600,
     "sparse_count_6000x24x77x32": sparse_count_6000x24x77x32,
 }
+
+
+# ---------------------------------------------------------------------------
+# batches of dense problems
+# ---------------------------------------------------------------------------
+
+def dense_problem(n_dims, rank, loss, seed, density=None):
+    """A dense problem with the recipe of its loss: Gaussian N(0,1) factors plus
+    0.1 noise; Poisson counts from Gamma(0.5,1) factors scaled to `density`
+    nonzeros; Bernoulli(odds) from U(0,1) factors scaled to mean probability
+    `density`.  Returns (X float64 dense, start factors, projection bound)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    dims = tuple(n_dims)
+    d = len(dims)
+    if loss == GAUSSIAN:
+        A = [rng.standard_normal((n, rank)) for n in dims]
+        X = _full(A) + 0.1 * rng.standard_normal(dims)
+        A0 = [rng.standard_normal((n, rank)) for n in dims]
+        return X, A0, -np.inf
+    if loss == POISSON:
+        A = [rng.gamma(0.5, 1.0, size=(n, rank)) for n in dims]
+        M = _full(A)
+        sub = rng.choice(M.reshape(-1), size=min(M.size, 200_000), replace=False)
+        target = density if density is not None else 5.0e6 / (6000 * 24 * 77 * 32)
+        lam = _bisect_scale(target, lambda l: float(np.mean(-np.expm1(-l * sub))))
+        X = rng.poisson(lam * M).astype(np.float64)
+        scale = lam ** (1.0 / d)
+        A0 = [rng.gamma(0.5, 1.0, size=(n, rank)) * scale for n in dims]
+        return X, A0, 0.0
+    A = [rng.random((n, rank)) for n in dims]
+    M = _full(A)
+    sub = rng.choice(M.reshape(-1), size=min(M.size, 200_000), replace=False)
+    target = density if density is not None else 0.002
+    lam = _bisect_scale(target, lambda l: float(np.mean(l * sub / (1.0 + l * sub))))
+    X = (rng.random(dims) < lam * M / (1.0 + lam * M)).astype(np.float64)
+    scale = lam ** (1.0 / d)
+    A0 = [rng.random((n, rank)) * scale for n in dims]
+    return X, A0, 0.0
+
+
+def batch_of_cubes(count=64, side_lo=20, side_hi=300, ranks=(4, 8, 16, 32), frac=0.02, seed_base=5000,
+                   cache=True):
+    """`count` dense 3-way cubes: side round(exp(U(ln lo, ln hi))), rank uniform
+    over `ranks`, loss b mod 3 (Gaussian, Poisson, Bernoulli-odds), uniform
+    sampling of ceil(frac * side^3) entries, FP32.  Problem b draws with seed
+    seed_base + 3 and problem_id b."""
+    rng = np.random.Generator(np.random.PCG64(seed_base + 4))
+    sides = np.rint(np.exp(rng.uniform(np.log(side_lo), np.log(side_hi), size=count))).astype(int)
+    rks = rng.choice(np.array(ranks), size=count)
+    out = []
+    for b in range(count):
+        n, r, loss = int(sides[b]), int(rks[b]), [GAUSSIAN, POISSON, BERNOULLI_ODDS][b % 3]
+
+        def make(n=n, r=r, loss=loss, b=b):
+            X, A0, lower = dense_problem((n, n, n), r, loss, seed=seed_base * 1000 + 1 + 7 * b)
+            z = {"X": X.astype(np.float32), "lower": np.array(lower)}
+            for k, a in enumerate(A0):
+                z[f"A{k}"] = a
+            return z
+
+        key = f"cube:{n}:{r}:{loss}:{seed_base}:{b}:v2"
+        z = _cached(key, make) if cache else make()
+        s = int(np.ceil(frac * n ** 3))
+        w = Workload(f"cube{b}_{n}_r{r}", (n, n, n), r, loss, UNIFORM, "f32", s=s, dense=z["X"],
+                     A_init=[z[f"A{k}"] for k in range(3)], seed=seed_base + 3, lower=float(z["lower"]))
+        w.problem_id = b
+        out.append(w)
+    return out

@@ -158,3 +158,84 @@ def test_sampled_adam_step_needs_factor_blocks_of_the_flat_array():
     assert call(0x90000) == 1 and b"flat parameter array" in L.gcp_last_error()
     # the right array passes the check and only then meets the (too small) workspace
     assert call(base) == 4 and b"workspace" in L.gcp_last_error()
+
+
+def _problem_struct(m, dims, rank, s, base):
+    """A dense FP32 uniform problem with fake (never dereferenced) device pointers."""
+    pr = m.GcpProblem()
+    pr.X = _dense_struct(m, dims, values=base)
+    pr.M.dtype, pr.M.rank = m.F32, rank
+    off = 0
+    for k, n in enumerate(dims):
+        pr.M.A[k] = base + 0x100000 + 4 * off
+        off += n * rank
+    pr.cfg.sampler, pr.cfg.s = m.UNIFORM, s
+    pr.loss, pr.eps, pr.lower = 0, 1e-10, -math.inf
+    pr.A, pr.B, pr.C = base + 0x100000, base + 0x200000, base + 0x300000
+    return pr
+
+
+def _plan(m, L, probs, tune):
+    arr = (m.GcpProblem * len(probs))(*probs)
+    h = ctypes.c_void_p()
+    st = L.gcp_batched_create(arr, len(probs), ctypes.byref(tune), ctypes.byref(h))
+    assert st == 0, L.gcp_last_error()
+    try:
+        assert L.gcp_batched_workspace_bytes(h) > 0
+        nb, nu = ctypes.c_int64(), ctypes.c_int64()
+        assert L.gcp_batched_plan(h, ctypes.byref(nb), ctypes.byref(nu), None, None, None) == 0
+        import numpy as np
+        bp = np.zeros(nb.value + 1, np.int64)
+        up = np.zeros(nu.value, np.int32)
+        ui = np.zeros((nu.value, 2), np.int64)
+        assert L.gcp_batched_plan(h, None, None, bp.ctypes.data, up.ctypes.data, ui.ctypes.data) == 0
+        return bp, up, ui
+    finally:
+        L.gcp_batched_destroy(h)
+
+
+@pytest.mark.parametrize("schedule,unit_items", [(0, 0), (1, 1), (1, 7), (1, 64)])
+def test_batch_plan_covers_every_item_once(schedule, unit_items):
+    """Host planning of a batch: every 64-sample item of every problem lies in
+    exactly one unit, each workgroup walks its units in problem order, and the
+    contiguous schedule gives every workgroup about the same estimated cost."""
+    m = _lib()
+    L = m.lib()
+    import numpy as np
+    rng = np.random.default_rng(3)
+    specs = [(int(n), int(r), int(s)) for n, r, s in zip(rng.integers(5, 120, 23), rng.choice([1, 4, 9, 32], 23),
+                                                          rng.integers(0, 60_000, 23))]
+    specs[5] = (40, 8, 0)                                    # a problem with no samples
+    probs = [_problem_struct(m, (n, n + 1, n + 2), r, s, 0x10000000 * (b + 1)) for b, (n, r, s) in enumerate(specs)]
+    tune = m.GcpBatchTuning()
+    tune.threads, tune.unit_items, tune.schedule = 1024, unit_items, schedule
+    bp, up, ui = _plan(m, L, probs, tune)
+    nblocks = len(bp) - 1
+    assert bp[0] == 0 and bp[-1] == len(up) and np.all(np.diff(bp) >= 0)
+    items = [-(-s // 64) for _, _, s in specs]
+    seen = [np.zeros(n, np.int32) for n in items]
+    cost = np.zeros(nblocks)
+    for w in range(nblocks):
+        units = range(bp[w], bp[w + 1])
+        probs_w = [up[u] for u in units]
+        assert probs_w == sorted(probs_w)                    # problem order inside a workgroup
+        for u in units:
+            b, (i0, i1) = up[u], ui[u]
+            assert 0 <= i0 < i1 <= items[b]
+            seen[b][i0:i1] += 1
+            cost[w] += (i1 - i0) * 3 * max(specs[b][1], 4)
+    for b in range(len(specs)):
+        assert np.all(seen[b] == 1), b
+    if schedule == 0:
+        # a workgroup's cost exceeds the even share by at most one item of the costliest problem
+        share = cost.sum() / nblocks
+        assert cost.max() <= share + 3 * 32 + 1e-9
+        # contiguous runs: (workgroup, problem) pairs are at most workgroups + problems
+        pairs = len({(w, up[u]) for w in range(nblocks) for u in range(bp[w], bp[w + 1])})
+        assert pairs <= nblocks + len(specs)
+    bad = m.GcpBatchTuning()
+    bad.schedule = 7
+    arr = (m.GcpProblem * 1)(probs[0])
+    h = ctypes.c_void_p()
+    assert L.gcp_batched_create(arr, 1, ctypes.byref(bad), ctypes.byref(h)) == 1
+    assert b"schedule" in L.gcp_last_error()

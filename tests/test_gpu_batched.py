@@ -1,0 +1,190 @@
+"""GPU parity of batches (gcp_batched_*): one launch pair advances many problems.
+
+Every problem of a batch draws the samples it would draw alone, so its batched
+gradient and Adam step must agree with the single-problem calls and with the
+oracle: 1e-5 relative (FP32 factors), 1e-12 (FP64).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+import paper_1906_01687_amd as gcp
+from paper_1906_01687_amd import autotune
+from gpu_cases import TORCH_DT, host_rounded, rel_fro, small_sparse
+
+pytestmark = pytest.mark.gpu
+
+
+def announce(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def make_problem(w, pid, dtype=None, keep_grad=True):
+    dev = torch.device("cuda:0")
+    dtype = dtype or w.dtype
+    vdt = torch.float64 if dtype == "f64" else torch.float32
+    if w.dense is not None:
+        X = gcp.dense_tensor(torch.as_tensor(np.ascontiguousarray(w.dense)).to(vdt).to(dev))
+    else:
+        X = gcp.coo_tensor(w.dims, torch.as_tensor(np.ascontiguousarray(w.coo_idx).view(np.int32)).to(dev),
+                           torch.as_tensor(w.coo_val).to(vdt).to(dev))
+    M = gcp.Factors(w.dims, w.rank, TORCH_DT[dtype], dev, init=w.A_init)
+    cfg = gcp.sampling(w.sampler, s=w.s, p=w.p, q=w.q, seed=w.seed, problem_id=pid)
+    return gcp.Problem(w.loss, X, M, cfg, lower=w.lower, keep_grad=keep_grad)
+
+
+def mixed_workloads(dtype="f32"):
+    """Dense cubes of several sides, ranks and losses plus sparse semi-stratified problems."""
+    out = []
+    specs = [(9, 1, 0), (17, 4, 1), (23, 7, 2), (31, 16, 0), (12, 33, 1), (40, 8, 2), (26, 5, 0)]
+    for b, (n, r, loss) in enumerate(specs):
+        X, A0, lower = synth.dense_problem((n, n, n), r, [synth.GAUSSIAN, synth.POISSON, synth.BERNOULLI_ODDS][loss],
+                                           seed=900 + b, density=0.05 if loss else None)
+        out.append(synth.Workload(f"cube{b}", (n, n, n), r, [synth.GAUSSIAN, synth.POISSON, synth.BERNOULLI_ODDS][loss],
+                                  synth.UNIFORM, dtype, s=max(37, int(0.03 * n ** 3)), dense=X, A_init=A0, seed=77,
+                                  lower=lower))
+    out.append(small_sparse("counts", dims=(41, 23, 17), rank=10, p=1500, q=2100, dtype=dtype))
+    out.append(small_sparse("binary", dims=(33, 29, 18), rank=6, p=900, q=1300, dtype=dtype,
+                            sampler=synth.SEMI_STRATIFIED))
+    return out
+
+
+def oracle_gradient(w, pid, iteration, dtype):
+    A64 = host_rounded(w.A_init, dtype)
+    if w.dense is not None:
+        dense = torch.as_tensor(np.asarray(w.dense)).to(torch.float64 if dtype == "f64" else torch.float32)
+        smp = oracle.sample(w.sampler, w.dims, dense=dense.to(torch.float64).numpy(), s=w.s, seed=w.seed,
+                            problem_id=pid, iteration=iteration)
+    else:
+        smp = oracle.sample(w.sampler, w.dims, coo_idx=np.asarray(w.coo_idx, dtype=np.int64),
+                            coo_val=np.asarray(w.coo_val, dtype=np.float64), p=w.p, q=w.q, seed=w.seed,
+                            problem_id=pid, iteration=iteration)
+    G, _ = oracle.grad(w.loss, w.dims, A64, smp, nnz=w.nnz, s=w.s, p=w.p, q=w.q)
+    return G
+
+
+@pytest.mark.parametrize("tune", [None, (256, 0, gcp.BATCH_CONTIGUOUS), (512, 0, gcp.BATCH_CONTIGUOUS),
+                                  (256, 8, gcp.BATCH_LPT), (512, 1, gcp.BATCH_LPT), (1024, 200, gcp.BATCH_LPT)])
+def test_batched_grad_matches_single_problem_calls(tune):
+    announce(f"batched gradient vs single-problem calls and the oracle, tune={tune}")
+    ws = mixed_workloads()
+    probs = [make_problem(w, b) for b, w in enumerate(ws)]
+    batch = gcp.Batch(probs, tune=tune)
+    for it in range(2):
+        batch.grad()
+        torch.cuda.synchronize()
+        assert int(batch.counter.item()) == it + 1
+        for b, (w, p) in enumerate(zip(ws, probs)):
+            cfg = gcp.sampling(w.sampler, s=w.s, p=w.p, q=w.q, seed=w.seed, problem_id=b, iteration=it)
+            single = gcp.sampled_grad(w.loss, p.X, p.M, cfg)
+            torch.cuda.synchronize()
+            Gb = p.M.grad_views(p.G)
+            err = max(rel_fro(Gb, [s.detach().to(torch.float64).cpu().numpy() for s in single]))
+            assert err <= 1e-5, (b, it, err)
+            if it == 0:
+                err_o = max(rel_fro(Gb, oracle_gradient(w, b, it, "f32")))
+                assert err_o <= 1e-5, (b, err_o)
+    batch.close()
+
+
+def test_batched_fp64():
+    announce("batched gradient, FP64 factors")
+    ws = mixed_workloads(dtype="f64")[:5]
+    probs = [make_problem(w, b, dtype="f64") for b, w in enumerate(ws)]
+    batch = gcp.Batch(probs)
+    batch.grad()
+    torch.cuda.synchronize()
+    for b, (w, p) in enumerate(zip(ws, probs)):
+        err = max(rel_fro(p.M.grad_views(p.G), oracle_gradient(w, b, 0, "f64")))
+        assert err <= 1e-12, (b, err)
+    batch.close()
+
+
+def test_batched_adam_matches_single_problem_steps():
+    announce("batched Adam steps vs single-problem gcp_sampled_adam_step")
+    ws = mixed_workloads()
+    pa = [make_problem(w, b) for b, w in enumerate(ws)]
+    pb = [make_problem(w, b) for b, w in enumerate(ws)]
+    batch = gcp.Batch(pa)
+    singles = []
+    for b, (w, p) in enumerate(zip(ws, pb)):
+        adam = gcp.Adam(p.M, lr=0.01, lower=w.lower)
+        cfg = gcp.sampling(w.sampler, s=w.s, p=w.p, q=w.q, seed=w.seed, problem_id=b)
+        singles.append((gcp.SampledAdamStep(w.loss, p.X, p.M, cfg, adam), adam))
+    for it in range(3):
+        before = [p.M.flat.to(torch.float64).clone() for p in pb]
+        batch.adam_step(lr=0.01)
+        for step, _ in singles:
+            step(iteration=it)
+        torch.cuda.synchronize()
+        assert int(batch.state[0]) == it + 1
+        for b in range(len(ws)):
+            xa, xb = pa[b].M.flat.to(torch.float64), pb[b].M.flat.to(torch.float64)
+            err = float((xa - xb).norm() / (xb - before[b]).norm().clamp_min(1e-30))
+            assert err <= 1e-5, (b, it, err)
+    batch.close()
+
+
+def test_batched_graph_replay():
+    announce("hipGraph replay of a batched Adam step")
+    ws = mixed_workloads()[:6]
+    pa = [make_problem(w, b) for b, w in enumerate(ws)]
+    pb = [make_problem(w, b) for b, w in enumerate(ws)]
+    ba, bb = gcp.Batch(pa), gcp.Batch(pb)
+    ba.adam_step()
+    bb.adam_step()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        ba.adam_step()
+    for rep in range(3):
+        graph.replay()
+        bb.adam_step()
+        torch.cuda.synchronize()
+        for b in range(len(ws)):
+            torch.testing.assert_close(pa[b].M.flat, pb[b].M.flat, rtol=1e-5, atol=1e-7)
+        _ = sum(float(p.M.flat.sum()) for p in pa)   # unrelated eager work between replays
+    ba.close()
+    bb.close()
+
+
+def test_batched_large_problems_use_fp32_lds_and_atomics():
+    announce("batched: problems beyond the FP64 LDS budget (FP32 LDS, device atomics)")
+    # (700+20+15) x 32: 188 KB in FP64 -> FP32 LDS; (1500+35) x 32: 196 KB even in FP32 -> atomics
+    specs = [(700, 32), (1500, 32), (50, 4)]
+    ws = []
+    for b, (n, r) in enumerate(specs):
+        dims = (n, 20, 15)
+        X, A0, lower = synth.dense_problem(dims, r, synth.GAUSSIAN, seed=950 + b)
+        ws.append(synth.Workload(f"big{b}", dims, r, synth.GAUSSIAN, synth.UNIFORM, "f32", s=40_000, dense=X,
+                                 A_init=A0, seed=78))
+    probs = [make_problem(w, b) for b, w in enumerate(ws)]
+    batch = gcp.Batch(probs)
+    batch.grad()
+    torch.cuda.synchronize()
+    for b, (w, p) in enumerate(zip(ws, probs)):
+        err = max(rel_fro(p.M.grad_views(p.G), oracle_gradient(w, b, 0, "f32")))
+        assert err <= 1e-5, (b, err)
+    batch.close()
+
+
+def test_autotune_picks_a_candidate(tmp_path):
+    announce("autotune over two launch shapes")
+    ws = mixed_workloads()[:4]
+    probs = [make_problem(w, b) for b, w in enumerate(ws)]
+    before = [p.M.flat.clone() for p in probs]
+    cache = str(tmp_path / "tune.json")
+    cands = [(256, 8, gcp.BATCH_LPT), (1024, 0, gcp.BATCH_CONTIGUOUS)]
+    best, times = autotune.tune_batch(probs, candidates=cands, steps=3, cache_path=cache)
+    assert best in cands and len(times) == 2
+    best2, _ = autotune.tune_batch(probs, candidates=[(512, 16, gcp.BATCH_LPT)], cache_path=cache)   # cached
+    assert best2 == best
+    torch.cuda.synchronize()
+    for p, a in zip(probs, before):
+        assert torch.equal(p.M.flat, a)          # tuning leaves the parameters alone
