@@ -124,7 +124,8 @@ typedef struct gcp_factors {
     int32_t dtype;               /* storage: GCP_F32, GCP_F64 or GCP_BF16 */
     int32_t reserved;            /* set to 0 */
     int64_t rank;                /* r, 1..GCP_MAX_RANK */
-    const void *A[GCP_MAX_D];    /* A[k]: dims[k] x rank, row-major, device */
+    const void *A[GCP_MAX_D];    /* A[k]: dims[k] x rank, row-major, device; each
+                                    block below 4 GiB (else GCP_ERR_UNSUPPORTED) */
 } gcp_factors;
 
 /* What one stochastic gradient samples. */

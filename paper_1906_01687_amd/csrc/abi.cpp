@@ -167,8 +167,13 @@ static gcp_status check_factors(const gcp_tensor* X, const gcp_factors* M) {
         return set_error(GCP_ERR_INVALID_ARG, "M->dtype must be GCP_F32, GCP_F64 or GCP_BF16");
     if (M->rank < 1) return set_error(GCP_ERR_INVALID_ARG, "M->rank must be >= 1");
     if (M->rank > GCP_MAX_RANK) return set_error(GCP_ERR_UNSUPPORTED, "M->rank above 64 is not supported");
-    for (int k = 0; k < X->d; ++k)
+    const uint64_t esz = M->dtype == GCP_F64 ? 8 : (M->dtype == GCP_F32 ? 4 : 2);
+    for (int k = 0; k < X->d; ++k) {
         if (!M->A[k]) return set_error(GCP_ERR_INVALID_ARG, "M->A[" + std::to_string(k) + "] is NULL");
+        // factor rows are gathered through buffer descriptors with 32-bit byte offsets
+        if ((uint64_t)X->dims[k] * (uint64_t)M->rank * esz > 0xFFFFFFFFull)
+            return set_error(GCP_ERR_UNSUPPORTED, "factor block " + std::to_string(k) + " exceeds 4 GiB");
+    }
     return GCP_OK;
 }
 

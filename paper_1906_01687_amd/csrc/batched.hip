@@ -112,14 +112,16 @@ __global__ __launch_bounds__(1024) void batched_grad_kernel(BatchGradArgs ba) {
         const uint64_t iter = a.iter + ctr;
         for (int64_t item = un.item_begin + wib; item < un.item_end; item += nwib) {
             const int64_t c = item * kWave + lane;
-            uint32_t i[D];
-#pragma unroll
-            for (int k = 0; k < D; ++k) i[k] = 0;
-            T x = T(0);
-            int code = -1;
-            if (c < a.n_direct) produce<D, VT, T>(a, iter, c, i, x, code);
-            if (f32) evaluate_and_scatter<D, FT, false, float>(a, reinterpret_cast<float*>(lds), i, x, code, T(0), fsum);
-            else evaluate_and_scatter<D, FT, false, double>(a, lds, i, x, code, T(0), fsum);
+            Sample<D, T> smp = no_sample<D, T>();
+            if (c < a.n_direct) {
+                uint32_t i[D];
+                T x;
+                int code;
+                produce<D, VT, T>(a, iter, c, i, x, code);
+                smp = make_sample<D, T>(a, i, x, code);
+            }
+            if (f32) evaluate_and_scatter<D, FT, false, float>(a, reinterpret_cast<float*>(lds), smp, fsum);
+            else evaluate_and_scatter<D, FT, false, double>(a, lds, smp, fsum);
         }
         const int32_t next = u + 1 < u_end ? ba.units[u + 1].problem : -1;
         if (next != un.problem) {

@@ -106,24 +106,25 @@ __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
     T fsum = T(0);
 
     for (int64_t item = wave; item < n_items; item += nwave) {
-        uint32_t i[D];
-#pragma unroll
-        for (int k = 0; k < D; ++k) i[k] = 0;
-        T x = T(0), ylist = T(0);
-        int code = -1;
+        Sample<D, T> smp = no_sample<D, T>();
         if (item < a.n_direct_items) {
             const int64_t c = item * kWave + lane;
             if (c < a.n_direct) {
                 if constexpr (LIST) {
+                    uint32_t i[D];
 #pragma unroll
                     for (int k = 0; k < D; ++k) i[k] = a.idx[c * D + k];
-                    ylist = static_cast<const T*>(a.ytilde)[c];
-                    code = 0;
+                    smp = make_sample<D, T>(a, i, static_cast<const T*>(a.ytilde)[c], GCP_STRATUM_UNIFORM);
+                    smp.w = T(1);
                 } else {
+                    uint32_t i[D];
+                    T x;
+                    int code;
                     produce<D, VT, T>(a, iter, c, i, x, code);
+                    smp = make_sample<D, T>(a, i, x, code);
                 }
             }
-            evaluate_and_scatter<D, FT, LIST>(a, lds, i, x, code, ylist, fsum);
+            evaluate_and_scatter<D, FT, LIST>(a, lds, smp, fsum);
         } else if constexpr (!LIST) {
             // stratified zeros: the accepted candidates of one 64-candidate chunk,
             // staged in counter order by the count kernel
@@ -131,22 +132,24 @@ __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
             const uint64_t rank = chunk_prefix(a, chunk) + (uint64_t)lane;
             const uint32_t cnt = a.chunk_count[chunk];
             if ((uint32_t)lane < cnt && rank < (uint64_t)a.q) {
+                uint32_t i[D];
 #pragma unroll
                 for (int k = 0; k < D; ++k) i[k] = a.zstage[((int64_t)chunk * kWave + lane) * D + k];
-                code = GCP_STRATUM_ZERO;
+                smp = make_sample<D, T>(a, i, T(0), GCP_STRATUM_ZERO);
             }
-            evaluate_and_scatter<D, FT, false>(a, lds, i, x, code, ylist, fsum);
+            evaluate_and_scatter<D, FT, false>(a, lds, smp, fsum);
             if (chunk == a.n_zero_items - 1) {
                 // first batch short of q zeros: continue the counter stream (wave-uniform loop)
                 uint64_t filled = batch_total(a);
                 uint64_t base = (uint64_t)a.ncand;
                 for (int64_t t = 0; t < kRejMaxRefillTiles * 16 && filled < (uint64_t)a.q; ++t) {
                     const uint64_t jj = base + lane;
+                    uint32_t i[D];
                     const bool ok = candidate_accepted<D>(a.dims, a.tab, a.seed, a.pid, iter, jj, i);
                     const uint64_t b2 = __ballot(ok);
                     const uint64_t rk = filled + __popcll(b2 & ((1ull << lane) - 1ull));
                     const int cz = (ok && rk < (uint64_t)a.q) ? GCP_STRATUM_ZERO : -1;
-                    evaluate_and_scatter<D, FT, false>(a, lds, i, x, cz, ylist, fsum);
+                    evaluate_and_scatter<D, FT, false>(a, lds, make_sample<D, T>(a, i, T(0), cz), fsum);
                     filled += __popcll(b2);
                     base += kWave;
                 }

@@ -91,12 +91,182 @@ __device__ __forceinline__ void produce(const GradArgs& a, uint64_t iter, int64_
     }
 }
 
-// Phase B: the wave's 64 samples (one per lane in i/x/code/ylist) are
-// evaluated and scattered into the LDS partial (accumulator type LT) for
-// privatised modes and into a.acc with device atomics for the others.  Every
-// lane of the wave must call this.  Passes
-// are taken kBatch at a time so that the row gathers of a batch are all in
-// flight before any of them is consumed.
+// Add into an LDS partial.  FP64 uses the native LDS atomic.  FP32 goes
+// through a compare-and-swap loop on the 32-bit word: on gfx950 the native
+// LDS FP32 atomic add takes about 190 cycles per wave instruction whatever the
+// address pattern, against 14-27 for this loop and 8-21 for the FP64 atomic
+// (measured with 16 waves per CU).  The loop compares bit patterns, so it ends
+// also when the word holds a NaN.
+__device__ __forceinline__ void lds_add(double* p, double v) { atomicAdd(p, v); }
+
+__device__ __forceinline__ void lds_add(float* p, float v) {
+    unsigned* w = reinterpret_cast<unsigned*>(p);
+    unsigned old = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    unsigned assumed;
+    do {
+        assumed = old;
+        old = atomicCAS(w, assumed, __float_as_uint(__uint_as_float(assumed) + v));
+    } while (old != assumed);
+}
+
+// One sample as phase A hands it to phase B.
+template <int D, typename T>
+struct Sample {
+    uint32_t q[D];  // first element of the sample's row of mode k: i_k * r
+    T x;            // data value (list mode: ytilde)
+    T w;            // stratum weight, negated for a corrected nonzero (g(x,m) - g(0,m)); 0: no sample
+};
+
+template <int D, typename T>
+__device__ __forceinline__ Sample<D, T> no_sample() {
+    Sample<D, T> s;
+#pragma unroll
+    for (int k = 0; k < D; ++k) s.q[k] = 0;
+    s.x = T(0);
+    s.w = T(0);
+    return s;
+}
+
+template <int D, typename T>
+__device__ __forceinline__ Sample<D, T> make_sample(const GradArgs& a, const uint32_t (&i)[D], T x, int code) {
+    Sample<D, T> s;
+#pragma unroll
+    for (int k = 0; k < D; ++k) s.q[k] = i[k] * (uint32_t)a.r;
+    s.x = x;
+    if (code < 0) {
+        s.w = T(0);
+    } else {
+        const T w = pick_weight<T>(a.w, code);
+        s.w = code == GCP_STRATUM_NZ_CORR ? -w : w;
+    }
+    return s;
+}
+
+// Cross-lane helpers.  Broadcasts read another lane with ds_bpermute; group
+// sums run on the VALU: DPP quad permutations, half-row and row mirrors within
+// 16 lanes, then the gfx950 row-pair (permlane16) and half-wave (permlane32)
+// swaps, whose two results add to the sum over both rows or halves.
+__device__ __forceinline__ uint32_t bcast(uint32_t v, int addr) {
+    return (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)v);
+}
+__device__ __forceinline__ float bcast(float v, int addr) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+__device__ __forceinline__ double bcast(double v, int addr) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = bcast((uint32_t)u, addr), hi = bcast((uint32_t)(u >> 32), addr);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+template <int HALF>
+__device__ __forceinline__ float swap_sum(float v) {
+    const int b = __float_as_int(v);
+    const auto p = HALF == 16 ? __builtin_amdgcn_permlane16_swap(b, b, false, false)
+                              : __builtin_amdgcn_permlane32_swap(b, b, false, false);
+    return __int_as_float((int)p[0]) + __int_as_float((int)p[1]);
+}
+template <int HALF>
+__device__ __forceinline__ double swap_sum(double v) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const int lo = (int)(uint32_t)u, hi = (int)(uint32_t)(u >> 32);
+    const auto pl = HALF == 16 ? __builtin_amdgcn_permlane16_swap(lo, lo, false, false)
+                               : __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto ph = HALF == 16 ? __builtin_amdgcn_permlane16_swap(hi, hi, false, false)
+                               : __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    const double a = __longlong_as_double((long long)(((uint64_t)(uint32_t)ph[0] << 32) | (uint32_t)pl[0]));
+    const double b = __longlong_as_double((long long)(((uint64_t)(uint32_t)ph[1] << 32) | (uint32_t)pl[1]));
+    return a + b;
+}
+
+// Sum over the aligned group of lps lanes (a power of two); every lane of the
+// group gets the same bits.  All 64 lanes must be active.
+template <typename T>
+__device__ __forceinline__ T group_sum(T m, int lps) {
+    if (lps >= 2) m += dpp<0xB1>(m);   // quad_perm [1,0,3,2]
+    if (lps >= 4) m += dpp<0x4E>(m);   // quad_perm [2,3,0,1]
+    if (lps >= 8) m += dpp<0x141>(m);  // row_half_mirror
+    if (lps >= 16) m += dpp<0x140>(m); // row_mirror
+    if (lps >= 32) m = swap_sum<16>(m);
+    if (lps >= 64) m = swap_sum<32>(m);
+    return m;
+}
+
+// x / y: IEEE division in FP64; reciprocal (1 ulp) and product in FP32.
+__device__ __forceinline__ double quot(double x, double y) { return x / y; }
+__device__ __forceinline__ float quot(float x, float y) { return x * __builtin_amdgcn_rcpf(y); }
+
+// w * g(x, m) for the loss's derivative g (Sec. 1 and 4.2); for a corrected
+// nonzero of semi-stratified sampling (Sec. 4.3, Alg. 3), w * (g(x, m) -
+// g(0, m)), which keeps only the part of g that depends on x.
+template <typename T>
+__device__ __forceinline__ T weighted_g(int loss, T x, T m, T w, T eps) {
+    const bool corr = w < T(0);
+    T g;
+    if (loss == GCP_LOSS_GAUSSIAN) {
+        g = corr ? T(-2) * x : T(2) * (m - x);
+    } else {
+        const T t = quot(x, m + eps);
+        const T base = loss == GCP_LOSS_BERNOULLI_ODDS ? quot(T(1), m + T(1)) : T(1);
+        g = corr ? -t : base - t;
+    }
+    return (corr ? -w : w) * g;
+}
+
+// Element of a factor block through a buffer resource (32-bit byte offset).
+template <typename FT> struct RowLoad;
+template <> struct RowLoad<float> {
+    static __device__ __forceinline__ float at(__amdgpu_buffer_rsrc_t rs, uint32_t e) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, e * 4u, 0, 0));
+    }
+};
+template <> struct RowLoad<double> {
+    static __device__ __forceinline__ double at(__amdgpu_buffer_rsrc_t rs, uint32_t e) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, e * 8u, 0, 0);
+        return __longlong_as_double((long long)(((uint64_t)v[1] << 32) | v[0]));
+    }
+};
+template <> struct RowLoad<bf16_t> {
+    static __device__ __forceinline__ float at(__amdgpu_buffer_rsrc_t rs, uint32_t e) {
+        return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rs, e * 2u, 0, 0) << 16);
+    }
+};
+
+constexpr int kBufferWord3 = 0x00020000;  // raw buffer, 32-bit elements, gfx9 family
+
+// Values that are the same on every lane but that the compiler cannot prove
+// uniform (fields of an argument block read from global memory) are moved to
+// scalar registers, so buffer descriptors and branches built from them stay
+// scalar.
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ int64_t uni(int64_t v) {
+    const uint32_t lo = uni((uint32_t)(uint64_t)v), hi = uni((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <typename P>
+__device__ __forceinline__ P* uni(P* p) {
+    return reinterpret_cast<P*>((uintptr_t)uni((int64_t)(uintptr_t)p));
+}
+
+// Phase B: the wave's 64 samples (one per lane in smp) are evaluated and
+// scattered into the LDS partial (accumulator type LT) for privatised modes
+// and into a.acc with device atomics for the others.  A sample takes a group
+// of lps lanes, lane j holding column j of its rows, so one pass covers 64/lps
+// samples.  Passes are taken kBatch at a time so that the row gathers of a
+// batch are all in flight before any of them is consumed.  Every lane of the
+// wave must call this.
 #ifndef GCP_PASS_BATCH
 #define GCP_PASS_BATCH 4
 #endif
@@ -104,44 +274,57 @@ constexpr int kBatch = GCP_PASS_BATCH;
 
 template <int D, typename FT, bool LIST, typename LT = double>
 __device__ __forceinline__ void evaluate_and_scatter(const GradArgs& a, LT* __restrict__ lds,
-                                                     const uint32_t (&i)[D],
-                                                     typename Compute<FT>::type x, int code,
-                                                     typename Compute<FT>::type ylist,
+                                                     const Sample<D, typename Compute<FT>::type>& smp,
                                                      typename Compute<FT>::type& fsum) {
     using T = typename Compute<FT>::type;
     const int lane = threadIdx.x & (kWave - 1);
-    const int lps = a.lps;
+    const int lps = uni((int32_t)a.lps);
     const int spw = kWave / lps;
     const int slot = lane / lps;
-    const int j = lane & (lps - 1);
-    const int r = a.r;
+    const uint32_t j = (uint32_t)(lane & (lps - 1));
+    const int r = uni((int32_t)a.r);
+    const int loss = uni((int32_t)a.loss);
+    const uint32_t priv = uni(a.priv_mask);
+    const bool colj = (int)j < r;
     const T eps = (T)a.eps;
+    __amdgpu_buffer_rsrc_t rs[D];
+    uint32_t lbase[D];
+    double* accj[D];
+    double* const acc = uni(a.acc);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const uint64_t bytes = (uint64_t)uni(a.dims.n[k]) * (uint64_t)r * sizeof(FT);
+        rs[k] = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(uni(a.A[k])), (short)0,
+                                                  (int)(bytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)bytes),
+                                                  kBufferWord3);
+        lbase[k] = (uint32_t)((uni(a.lds_off[k]) + (int64_t)j) * (int64_t)sizeof(LT));
+        accj[k] = acc ? acc + uni(a.acc_off[k]) + j : nullptr;
+    }
+    char* const lbytes = reinterpret_cast<char*>(lds);
     for (int p0 = 0; p0 < lps; p0 += kBatch) {
-        uint32_t ii[kBatch][D];
-        int cc[kBatch];
-        T xx[kBatch], yy[kBatch];
+        uint32_t qq[kBatch][D];
+        T xx[kBatch], ww[kBatch];
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
-            const int pass = p0 + u < lps ? p0 + u : 0;
-            const int src = pass * spw + slot;
+            const bool pass_ok = p0 + u < lps;
+            const int addr = ((pass_ok ? p0 + u : 0) * spw + slot) << 2;
 #pragma unroll
-            for (int k = 0; k < D; ++k) ii[u][k] = __shfl(i[k], src);
-            cc[u] = p0 + u < lps ? __shfl(code, src) : -1;
-            if constexpr (LIST) yy[u] = __shfl(ylist, src);
-            else xx[u] = __shfl(x, src);
+            for (int k = 0; k < D; ++k) qq[u][k] = bcast(smp.q[k], addr);
+            xx[u] = bcast(smp.x, addr);
+            const T wv = bcast(smp.w, addr);
+            ww[u] = pass_ok ? wv : T(0);
         }
         T av[kBatch][D];
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
-            const bool col = cc[u] >= 0 && j < r;
 #pragma unroll
-            for (int k = 0; k < D; ++k)
-                av[u][k] = col ? widen(static_cast<const FT*>(a.A[k])[(size_t)ii[u][k] * r + j]) : T(0);
+            for (int k = 0; k < D; ++k) {
+                const T v = RowLoad<FT>::at(rs[k], qq[u][k] + j);
+                av[u][k] = colj ? v : T(0);
+            }
         }
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
-            const bool live = cc[u] >= 0;
-            const bool col = live && j < r;
             T pre[D], suf[D];
             pre[0] = T(1);
 #pragma unroll
@@ -149,31 +332,28 @@ __device__ __forceinline__ void evaluate_and_scatter(const GradArgs& a, LT* __re
             suf[D - 1] = T(1);
 #pragma unroll
             for (int k = D - 2; k >= 0; --k) suf[k] = suf[k + 1] * av[u][k + 1];
+            const bool live = ww[u] != T(0);
             T y;
             if constexpr (LIST) {
-                y = yy[u];
+                y = xx[u];
             } else {
-                T m = pre[D - 1] * av[u][D - 1];
-                for (int o = lps >> 1; o > 0; o >>= 1) m += __shfl_xor(m, o);
-                const T w = pick_weight<T>(a.w, cc[u]);
-                T g = loss_g<T>(a.loss, xx[u], m, eps);
-                const bool corr = cc[u] == GCP_STRATUM_NZ_CORR;
-                if (corr) g -= loss_g<T>(a.loss, T(0), m, eps);
-                y = w * g;
+                const T m = group_sum(pre[D - 1] * av[u][D - 1], lps);
+                y = weighted_g(loss, xx[u], m, ww[u], eps);
                 if (a.loss_sum && live && j == 0) {
-                    T f = loss_f<T>(a.loss, xx[u], m, eps);
-                    if (corr) f -= loss_f<T>(a.loss, T(0), m, eps);
-                    fsum += w * f;
+                    const bool corr = ww[u] < T(0);
+                    T f = loss_f<T>(loss, xx[u], m, eps);
+                    if (corr) f -= loss_f<T>(loss, T(0), m, eps);
+                    fsum += (corr ? -ww[u] : ww[u]) * f;
                 }
             }
-            if (col) {
+            if (live && colj) {
 #pragma unroll
                 for (int k = 0; k < D; ++k) {
-                    const double v = (double)(y * pre[k] * suf[k]);
-                    if ((a.priv_mask >> k) & 1u)
-                        atomicAdd(&lds[a.lds_off[k] + (int64_t)ii[u][k] * r + j], (LT)v);
+                    const T v = y * (pre[k] * suf[k]);
+                    if ((priv >> k) & 1u)
+                        lds_add(reinterpret_cast<LT*>(lbytes + lbase[k] + qq[u][k] * (uint32_t)sizeof(LT)), (LT)v);
                     else
-                        unsafeAtomicAdd(&a.acc[a.acc_off[k] + (int64_t)ii[u][k] * r + j], v);
+                        unsafeAtomicAdd(accj[k] + qq[u][k], (double)v);
                 }
             }
         }

@@ -100,6 +100,22 @@ def test_argument_errors_are_reported_without_launching():
     st = L.gcp_sampled_grad(0, ctypes.byref(t), ctypes.byref(M), ctypes.byref(cfg), 1e-10, G, None,
                             0x1000, 1 << 20, None)
     assert st == 2
+    # a factor block beyond 4 GiB: 2^25 rows x 64 columns x 4 bytes = 8 GiB
+    t = _dense_struct(m, (1 << 25, 4))
+    M.rank = 64
+    st = L.gcp_sampled_grad(0, ctypes.byref(t), ctypes.byref(M), ctypes.byref(cfg), 1e-10, G, None,
+                            0x1000, 1 << 20, None)
+    assert st == 2 and b"4 GiB" in L.gcp_last_error()
+    M.dtype = m.BF16                     # 2 bytes per value: exactly 4 GiB is still too large
+    st = L.gcp_sampled_grad(0, ctypes.byref(t), ctypes.byref(M), ctypes.byref(cfg), 1e-10, G, None,
+                            0x1000, 1 << 20, None)
+    assert st == 2 and b"4 GiB" in L.gcp_last_error()
+    t = _dense_struct(m, ((1 << 25) - 1, 4))   # 4 GiB - 128 bytes passes the size check
+    st = L.gcp_sampled_grad(0, ctypes.byref(t), ctypes.byref(M), ctypes.byref(cfg), 1e-10, G, None,
+                            0x1000, 1 << 20, None)
+    assert b"4 GiB" not in L.gcp_last_error()
+    M.dtype = m.F32
+    t = _dense_struct(m, (3, 4))
     # workspace too small
     M.rank = 4
     need = L.gcp_sampled_grad_workspace_bytes(ctypes.byref(t), ctypes.byref(M), ctypes.byref(cfg))
