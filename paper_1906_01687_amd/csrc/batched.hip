@@ -110,7 +110,7 @@ __global__ __launch_bounds__(1024) void batched_grad_kernel(BatchGradArgs ba) {
             __syncthreads();
         }
         const uint64_t iter = a.iter + ctr;
-        for (int64_t item = un.item_begin + wib; item < un.item_end; item += nwib) {
+        auto draw = [&](int64_t item) {
             const int64_t c = item * kWave + lane;
             Sample<D, T> smp = no_sample<D, T>();
             if (c < a.n_direct) {
@@ -120,8 +120,17 @@ __global__ __launch_bounds__(1024) void batched_grad_kernel(BatchGradArgs ba) {
                 produce<D, VT, T>(a, iter, c, i, x, code);
                 smp = make_sample<D, T>(a, i, x, code);
             }
-            if (f32) evaluate_and_scatter<D, FT, false, float>(a, reinterpret_cast<float*>(lds), smp, fsum);
-            else evaluate_and_scatter<D, FT, false, double>(a, lds, smp, fsum);
+            return smp;
+        };
+        int64_t item = un.item_begin + wib;
+        Sample<D, T> cur = item < un.item_end ? draw(item) : no_sample<D, T>();
+        for (; item < un.item_end; item += nwib) {
+            // the next item's gathers are in flight while this one is evaluated
+            Sample<D, T> nxt = item + nwib < un.item_end ? draw(item + nwib) : no_sample<D, T>();
+            to_rows(a, cur);
+            if (f32) evaluate_and_scatter<D, FT, false, float>(a, reinterpret_cast<float*>(lds), cur, fsum);
+            else evaluate_and_scatter<D, FT, false, double>(a, lds, cur, fsum);
+            cur = nxt;
         }
         const int32_t next = u + 1 < u_end ? ba.units[u + 1].problem : -1;
         if (next != un.problem) {

@@ -10,8 +10,8 @@
 // item in passes; in each pass a group of `lps` lanes (lps = the power of two
 // >= r) takes one sample and lane j of the group owns rank column j.  The
 // group gathers A_k(i_k, j) for every mode (one coalesced row read per mode),
-// forms the Hadamard product, reduces it over the group with xor shuffles to
-// get m_i, evaluates the weighted derivative, and scatters
+// forms the Hadamard product, reduces it over the group with DPP and
+// permlane swaps to get m_i, evaluates the weighted derivative, and scatters
 // ytilde * prod_{k' != k} A_k'(i_k', j) into every mode's gradient.  Leave-one-
 // out products come from prefix/suffix products, so no division.
 //
@@ -88,6 +88,46 @@ __device__ __forceinline__ uint64_t batch_total(const GradArgs& a) {
     return wave_sum_u64(s);
 }
 
+// Phase A of one item: its 64 samples, one per lane (raw indices; the caller
+// applies to_rows before evaluating).  Wave-uniform item index.
+template <int D, typename FT, typename VT, bool LIST>
+__device__ __forceinline__ Sample<D, typename Compute<FT>::type> item_sample(const GradArgs& a, uint64_t iter,
+                                                                             int64_t item) {
+    using T = typename Compute<FT>::type;
+    const int lane = threadIdx.x & (kWave - 1);
+    Sample<D, T> smp = no_sample<D, T>();
+    if (item < a.n_direct_items) {
+        const int64_t c = item * kWave + lane;
+        if (c < a.n_direct) {
+            uint32_t i[D];
+            if constexpr (LIST) {
+#pragma unroll
+                for (int k = 0; k < D; ++k) i[k] = a.idx[c * D + k];
+                smp = make_sample<D, T>(a, i, static_cast<const T*>(a.ytilde)[c], GCP_STRATUM_UNIFORM);
+                smp.w = T(1);
+            } else {
+                T x;
+                int code;
+                produce<D, VT, T>(a, iter, c, i, x, code);
+                smp = make_sample<D, T>(a, i, x, code);
+            }
+        }
+    } else if constexpr (!LIST) {
+        // stratified zeros: the accepted candidates of one 64-candidate chunk,
+        // staged in counter order by the count kernel
+        const int64_t chunk = item - a.n_direct_items;
+        const uint64_t rank = chunk_prefix(a, chunk) + (uint64_t)lane;
+        const uint32_t cnt = a.chunk_count[chunk];
+        if ((uint32_t)lane < cnt && rank < (uint64_t)a.q) {
+            uint32_t i[D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) i[k] = a.zstage[((int64_t)chunk * kWave + lane) * D + k];
+            smp = make_sample<D, T>(a, i, T(0), GCP_STRATUM_ZERO);
+        }
+    }
+    return smp;
+}
+
 template <int D, typename FT, typename VT, bool LIST>
 __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
     using T = typename Compute<FT>::type;
@@ -96,8 +136,6 @@ __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
     const int64_t nthreads = blockDim.x;
     // nothing in this kernel reads the step count; the reduction after it does
     if (a.adam_state && blockIdx.x == 0 && threadIdx.x == 0) a.adam_state[0] += 1;
-    for (int64_t e = threadIdx.x; e < a.lds_total; e += nthreads) lds[e] = 0.0;
-    __syncthreads();
 
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
     const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -105,41 +143,26 @@ __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
     const uint64_t iter = effective_iteration(a.iter, a.iter_ctr);
     T fsum = T(0);
 
+    // the first item's draws and gathers are issued before the LDS clear, so
+    // the clear runs under their latency
+    Sample<D, T> cur = wave < n_items ? item_sample<D, FT, VT, LIST>(a, iter, wave) : no_sample<D, T>();
+    {
+        double2* l2 = reinterpret_cast<double2*>(lds);
+        for (int64_t e = threadIdx.x; e < a.lds_total / 2; e += nthreads) l2[e] = double2{0.0, 0.0};
+        if ((a.lds_total & 1) && threadIdx.x == 0) lds[a.lds_total - 1] = 0.0;
+    }
+    __syncthreads();
+
     for (int64_t item = wave; item < n_items; item += nwave) {
-        Sample<D, T> smp = no_sample<D, T>();
-        if (item < a.n_direct_items) {
-            const int64_t c = item * kWave + lane;
-            if (c < a.n_direct) {
-                if constexpr (LIST) {
-                    uint32_t i[D];
-#pragma unroll
-                    for (int k = 0; k < D; ++k) i[k] = a.idx[c * D + k];
-                    smp = make_sample<D, T>(a, i, static_cast<const T*>(a.ytilde)[c], GCP_STRATUM_UNIFORM);
-                    smp.w = T(1);
-                } else {
-                    uint32_t i[D];
-                    T x;
-                    int code;
-                    produce<D, VT, T>(a, iter, c, i, x, code);
-                    smp = make_sample<D, T>(a, i, x, code);
-                }
-            }
-            evaluate_and_scatter<D, FT, LIST>(a, lds, smp, fsum);
-        } else if constexpr (!LIST) {
-            // stratified zeros: the accepted candidates of one 64-candidate chunk,
-            // staged in counter order by the count kernel
-            const int64_t chunk = item - a.n_direct_items;
-            const uint64_t rank = chunk_prefix(a, chunk) + (uint64_t)lane;
-            const uint32_t cnt = a.chunk_count[chunk];
-            if ((uint32_t)lane < cnt && rank < (uint64_t)a.q) {
-                uint32_t i[D];
-#pragma unroll
-                for (int k = 0; k < D; ++k) i[k] = a.zstage[((int64_t)chunk * kWave + lane) * D + k];
-                smp = make_sample<D, T>(a, i, T(0), GCP_STRATUM_ZERO);
-            }
-            evaluate_and_scatter<D, FT, false>(a, lds, smp, fsum);
-            if (chunk == a.n_zero_items - 1) {
-                // first batch short of q zeros: continue the counter stream (wave-uniform loop)
+        // the next item's gathers are in flight while this one is evaluated
+        const int64_t next = item + nwave;
+        Sample<D, T> nxt = next < n_items ? item_sample<D, FT, VT, LIST>(a, iter, next) : no_sample<D, T>();
+        to_rows(a, cur);
+        evaluate_and_scatter<D, FT, LIST>(a, lds, cur, fsum);
+        if constexpr (!LIST) {
+            if (a.n_zero_items > 0 && item == n_items - 1) {
+                // the last zero chunk, and the first batch held fewer than q
+                // zeros: continue the counter stream (wave-uniform loop)
                 uint64_t filled = batch_total(a);
                 uint64_t base = (uint64_t)a.ncand;
                 for (int64_t t = 0; t < kRejMaxRefillTiles * 16 && filled < (uint64_t)a.q; ++t) {
@@ -149,12 +172,15 @@ __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
                     const uint64_t b2 = __ballot(ok);
                     const uint64_t rk = filled + __popcll(b2 & ((1ull << lane) - 1ull));
                     const int cz = (ok && rk < (uint64_t)a.q) ? GCP_STRATUM_ZERO : -1;
-                    evaluate_and_scatter<D, FT, false>(a, lds, make_sample<D, T>(a, i, T(0), cz), fsum);
+                    Sample<D, T> z = make_sample<D, T>(a, i, T(0), cz);
+                    to_rows(a, z);
+                    evaluate_and_scatter<D, FT, false>(a, lds, z, fsum);
                     filled += __popcll(b2);
                     base += kWave;
                 }
             }
         }
+        cur = nxt;
     }
     if constexpr (!LIST) {
         if (a.loss_sum) {
@@ -167,7 +193,20 @@ __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
     // one dense partial per workgroup, plain stores (FP32 unless the factors are FP64)
     using PT = typename Partial<FT>::type;
     PT* __restrict__ part = static_cast<PT*>(a.partials) + (int64_t)blockIdx.x * a.lds_total;
-    for (int64_t e = threadIdx.x; e < a.lds_total; e += nthreads) part[e] = (PT)lds[e];
+    constexpr int kVec = 16 / sizeof(PT);  // elements per 16-byte store
+    if (a.lds_total % kVec == 0) {
+        for (int64_t e = threadIdx.x; e < a.lds_total / kVec; e += nthreads) {
+            if constexpr (kVec == 4) {
+                const double2 u = reinterpret_cast<const double2*>(lds)[2 * e];
+                const double2 v = reinterpret_cast<const double2*>(lds)[2 * e + 1];
+                reinterpret_cast<float4*>(part)[e] = float4{(float)u.x, (float)u.y, (float)v.x, (float)v.y};
+            } else {
+                reinterpret_cast<double2*>(part)[e] = reinterpret_cast<const double2*>(lds)[e];
+            }
+        }
+    } else {
+        for (int64_t e = threadIdx.x; e < a.lds_total; e += nthreads) part[e] = (PT)lds[e];
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -109,10 +109,13 @@ __device__ __forceinline__ void lds_add(float* p, float v) {
     } while (old != assumed);
 }
 
-// One sample as phase A hands it to phase B.
+// One sample as phase A hands it to phase B.  Phase A fills q with the raw
+// indices i_k, which may still be loads in flight; to_rows() turns them into
+// row offsets once they are needed, so a prefetched sample's gathers overlap
+// the evaluation of the previous one.
 template <int D, typename T>
 struct Sample {
-    uint32_t q[D];  // first element of the sample's row of mode k: i_k * r
+    uint32_t q[D];  // i_k from phase A; i_k * r after to_rows()
     T x;            // data value (list mode: ytilde)
     T w;            // stratum weight, negated for a corrected nonzero (g(x,m) - g(0,m)); 0: no sample
 };
@@ -131,7 +134,7 @@ template <int D, typename T>
 __device__ __forceinline__ Sample<D, T> make_sample(const GradArgs& a, const uint32_t (&i)[D], T x, int code) {
     Sample<D, T> s;
 #pragma unroll
-    for (int k = 0; k < D; ++k) s.q[k] = i[k] * (uint32_t)a.r;
+    for (int k = 0; k < D; ++k) s.q[k] = i[k];
     s.x = x;
     if (code < 0) {
         s.w = T(0);
@@ -140,6 +143,12 @@ __device__ __forceinline__ Sample<D, T> make_sample(const GradArgs& a, const uin
         s.w = code == GCP_STRATUM_NZ_CORR ? -w : w;
     }
     return s;
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void to_rows(const GradArgs& a, Sample<D, T>& s) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) s.q[k] *= (uint32_t)a.r;
 }
 
 // Cross-lane helpers.  Broadcasts read another lane with ds_bpermute; group
@@ -260,71 +269,48 @@ __device__ __forceinline__ P* uni(P* p) {
     return reinterpret_cast<P*>((uintptr_t)uni((int64_t)(uintptr_t)p));
 }
 
-// Phase B: the wave's 64 samples (one per lane in smp) are evaluated and
-// scattered into the LDS partial (accumulator type LT) for privatised modes
-// and into a.acc with device atomics for the others.  A sample takes a group
-// of lps lanes, lane j holding column j of its rows, so one pass covers 64/lps
-// samples.  Passes are taken kBatch at a time so that the row gathers of a
-// batch are all in flight before any of them is consumed.  Every lane of the
-// wave must call this.
-#ifndef GCP_PASS_BATCH
-#define GCP_PASS_BATCH 4
-#endif
-constexpr int kBatch = GCP_PASS_BATCH;
-
-template <int D, typename FT, bool LIST, typename LT = double>
-__device__ __forceinline__ void evaluate_and_scatter(const GradArgs& a, LT* __restrict__ lds,
-                                                     const Sample<D, typename Compute<FT>::type>& smp,
-                                                     typename Compute<FT>::type& fsum) {
-    using T = typename Compute<FT>::type;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int lps = uni((int32_t)a.lps);
-    const int spw = kWave / lps;
-    const int slot = lane / lps;
-    const uint32_t j = (uint32_t)(lane & (lps - 1));
-    const int r = uni((int32_t)a.r);
-    const int loss = uni((int32_t)a.loss);
-    const uint32_t priv = uni(a.priv_mask);
-    const bool colj = (int)j < r;
-    const T eps = (T)a.eps;
+// Per-call constants of phase B: lane layout, buffer descriptors of the
+// factor blocks and scatter bases of the lane's column.
+template <int D, typename LT>
+struct PhaseB {
+    int lps, spw, slot, r, loss;
+    uint32_t j, priv;
+    bool colj;
     __amdgpu_buffer_rsrc_t rs[D];
     uint32_t lbase[D];
     double* accj[D];
-    double* const acc = uni(a.acc);
+};
+
+template <int NB, int D, typename FT, bool LIST, typename LT>
+__device__ __forceinline__ void pass_batches(const GradArgs& a, const PhaseB<D, LT>& b, LT* __restrict__ lds,
+                                             const Sample<D, typename Compute<FT>::type>& smp,
+                                             typename Compute<FT>::type& fsum) {
+    using T = typename Compute<FT>::type;
+    const T eps = (T)a.eps;
+    for (int p0 = 0; p0 < b.lps; p0 += NB) {
+        uint32_t qq[NB][D];
+        T xx[NB], ww[NB];
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-        const uint64_t bytes = (uint64_t)uni(a.dims.n[k]) * (uint64_t)r * sizeof(FT);
-        rs[k] = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(uni(a.A[k])), (short)0,
-                                                  (int)(bytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)bytes),
-                                                  kBufferWord3);
-        lbase[k] = (uint32_t)((uni(a.lds_off[k]) + (int64_t)j) * (int64_t)sizeof(LT));
-        accj[k] = acc ? acc + uni(a.acc_off[k]) + j : nullptr;
-    }
-    char* const lbytes = reinterpret_cast<char*>(lds);
-    for (int p0 = 0; p0 < lps; p0 += kBatch) {
-        uint32_t qq[kBatch][D];
-        T xx[kBatch], ww[kBatch];
-#pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            const bool pass_ok = p0 + u < lps;
-            const int addr = ((pass_ok ? p0 + u : 0) * spw + slot) << 2;
+        for (int u = 0; u < NB; ++u) {
+            const bool pass_ok = p0 + u < b.lps;
+            const int addr = ((pass_ok ? p0 + u : 0) * b.spw + b.slot) << 2;
 #pragma unroll
             for (int k = 0; k < D; ++k) qq[u][k] = bcast(smp.q[k], addr);
             xx[u] = bcast(smp.x, addr);
             const T wv = bcast(smp.w, addr);
             ww[u] = pass_ok ? wv : T(0);
         }
-        T av[kBatch][D];
+        T av[NB][D];
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
+        for (int u = 0; u < NB; ++u) {
 #pragma unroll
             for (int k = 0; k < D; ++k) {
-                const T v = RowLoad<FT>::at(rs[k], qq[u][k] + j);
-                av[u][k] = colj ? v : T(0);
+                const T v = RowLoad<FT>::at(b.rs[k], qq[u][k] + b.j);
+                av[u][k] = b.colj ? v : T(0);
             }
         }
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
+        for (int u = 0; u < NB; ++u) {
             T pre[D], suf[D];
             pre[0] = T(1);
 #pragma unroll
@@ -337,26 +323,72 @@ __device__ __forceinline__ void evaluate_and_scatter(const GradArgs& a, LT* __re
             if constexpr (LIST) {
                 y = xx[u];
             } else {
-                const T m = group_sum(pre[D - 1] * av[u][D - 1], lps);
-                y = weighted_g(loss, xx[u], m, ww[u], eps);
-                if (a.loss_sum && live && j == 0) {
+                const T m = group_sum(pre[D - 1] * av[u][D - 1], b.lps);
+                y = weighted_g(b.loss, xx[u], m, ww[u], eps);
+                if (a.loss_sum && live && b.j == 0) {
                     const bool corr = ww[u] < T(0);
-                    T f = loss_f<T>(loss, xx[u], m, eps);
-                    if (corr) f -= loss_f<T>(loss, T(0), m, eps);
+                    T f = loss_f<T>(b.loss, xx[u], m, eps);
+                    if (corr) f -= loss_f<T>(b.loss, T(0), m, eps);
                     fsum += (corr ? -ww[u] : ww[u]) * f;
                 }
             }
-            if (live && colj) {
+            if (live && b.colj) {
 #pragma unroll
                 for (int k = 0; k < D; ++k) {
                     const T v = y * (pre[k] * suf[k]);
-                    if ((priv >> k) & 1u)
-                        lds_add(reinterpret_cast<LT*>(lbytes + lbase[k] + qq[u][k] * (uint32_t)sizeof(LT)), (LT)v);
+                    if ((b.priv >> k) & 1u)
+                        lds_add(reinterpret_cast<LT*>(reinterpret_cast<char*>(lds) + b.lbase[k] +
+                                                      qq[u][k] * (uint32_t)sizeof(LT)),
+                                (LT)v);
                     else
-                        unsafeAtomicAdd(accj[k] + qq[u][k], (double)v);
+                        unsafeAtomicAdd(b.accj[k] + qq[u][k], (double)v);
                 }
             }
         }
+    }
+}
+
+// Phase B: the wave's 64 samples (one per lane in smp, rows already formed by
+// to_rows) are evaluated and scattered into the LDS partial (accumulator type
+// LT) for privatised modes and into a.acc with device atomics for the others.
+// A sample takes a group of lps lanes, lane j holding column j of its rows, so
+// one pass covers 64/lps samples.  Passes are taken 2 to 8 at a time so that
+// the row gathers of a batch are all in flight before any of them is
+// consumed.  Every lane of the wave must call this.
+template <int D, typename FT, bool LIST, typename LT = double>
+__device__ __forceinline__ void evaluate_and_scatter(const GradArgs& a, LT* __restrict__ lds,
+                                                     const Sample<D, typename Compute<FT>::type>& smp,
+                                                     typename Compute<FT>::type& fsum) {
+    const int lane = threadIdx.x & (kWave - 1);
+    PhaseB<D, LT> b;
+    b.lps = uni((int32_t)a.lps);
+    b.spw = kWave / b.lps;
+    b.slot = lane / b.lps;
+    b.j = (uint32_t)(lane & (b.lps - 1));
+    b.r = uni((int32_t)a.r);
+    b.loss = uni((int32_t)a.loss);
+    b.priv = uni(a.priv_mask);
+    b.colj = (int)b.j < b.r;
+    double* const acc = uni(a.acc);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const uint64_t bytes = (uint64_t)uni(a.dims.n[k]) * (uint64_t)b.r * sizeof(FT);
+        b.rs[k] = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(uni(a.A[k])), (short)0,
+                                                    (int)(bytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)bytes),
+                                                    kBufferWord3);
+        b.lbase[k] = (uint32_t)((uni(a.lds_off[k]) + (int64_t)b.j) * (int64_t)sizeof(LT));
+        b.accj[k] = acc ? acc + uni(a.acc_off[k]) + b.j : nullptr;
+    }
+    // passes per batch: as many as keep a batch's registers (indices, value,
+    // weight and gathered entries) within about 64 VGPRs
+    using T = typename Compute<FT>::type;
+    constexpr int words = D + (2 + D) * (int)(sizeof(T) / 4);
+    constexpr int nb = words * 8 <= 64 ? 8 : (words * 4 <= 64 ? 4 : 2);
+    if constexpr (nb == 8) {
+        if (b.lps <= 4) pass_batches<4, D, FT, LIST, LT>(a, b, lds, smp, fsum);
+        else pass_batches<8, D, FT, LIST, LT>(a, b, lds, smp, fsum);
+    } else {
+        pass_batches<nb, D, FT, LIST, LT>(a, b, lds, smp, fsum);
     }
 }
 
