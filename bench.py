@@ -37,10 +37,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="sparse_binary_1000x800x600",
-                    help="sparse_binary_1000x800x600 | sparse_count_6000x24x77x32 | dense_gaussian_30x40x50 | batched_64_cubes")
+                    help="sparse_binary_1000x800x600 | sparse_count_6000x24x77x32 | dense_gaussian_30x40x50 | "
+                         "dense_gaussian_200x200x200x200[_bf16] | batched_64_cubes")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="bound on the oracle timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch every step eagerly")
+    ap.add_argument("--autograd", action="store_true",
+                    help="also time the step as SampledLoss forward + backward + Adam")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -98,13 +101,25 @@ def cpu_baseline(w, seconds: float):
     import oracle
     samples, t0, iters = 0, time.perf_counter(), 0
     kw = dict(s=w.s, p=w.p, q=w.q)
+    huge = w.dense is not None and w.dense.size > 100_000_000
     while True:
-        if w.dense is not None:
+        if huge:
+            # the oracle's uniform draws need no data; x is read from the same
+            # FP32 array (an FP64 copy of a 6.4 GB tensor per gradient would
+            # dominate the timing)
+            smp = oracle.sample(w.sampler, w.dims, coo_idx=np.zeros((0, w.d), dtype=np.int64),
+                                coo_val=np.zeros(0), seed=w.seed, iteration=iters, **kw)
+            smp.xval = w.dense[tuple(smp.idx.T)].astype(np.float64)
+        elif w.dense is not None:
             smp = oracle.sample(w.sampler, w.dims, dense=w.dense, seed=w.seed, iteration=iters, **kw)
         else:
             smp = oracle.sample(w.sampler, w.dims, coo_idx=w.coo_idx.astype(np.int64), coo_val=w.coo_val,
                                 seed=w.seed, iteration=iters, **kw)
-        A64 = [np.float32(a).astype(np.float64) for a in w.A_init] if w.dtype != "f64" else w.A_init
+        A64 = [np.float32(a).astype(np.float64) for a in w.A_init] if w.dtype == "f32" else w.A_init
+        if w.dtype == "bf16":
+            import torch
+            A64 = [torch.as_tensor(a).to(torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+                   for a in w.A_init]
         oracle.grad(w.loss, w.dims, A64, smp, nnz=w.nnz, **kw)
         samples += len(smp)
         iters += 1
@@ -305,6 +320,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    autograd = None
+    if args.autograd:
+        autograd = time_autograd(args, w, X, M, sampler_name, ms_per_step)
+
     traffic = profiled_traffic(w.name)
 
     cpu = None
@@ -334,7 +353,46 @@ def main():
                      "kernel_us": kernel_ms * 1e3, "algorithmic_bytes_per_launch": balg},
         "cpu_baseline": cpu,
     }
+    if autograd is not None:
+        out["autograd_step"] = autograd
     print(json.dumps(out), flush=True)
+
+
+def time_autograd(args, w, X, M, sampler_name, plain_ms):
+    """The same step as a torch.autograd graph: F = SampledLoss(param) (gcp_sample +
+    gcp_loss_grad), F.backward() (gcp_mttkrp adjoint), then gcp_adam_step on the
+    gradient; timed over K eager steps against the plain fused step."""
+    import torch
+    import paper_1906_01687_amd as gcp
+
+    dev = X.values.device
+    counter = torch.zeros(1, dtype=torch.int64, device=dev)
+    cfg = gcp.sampling(sampler_name, s=w.s, p=w.p, q=w.q, seed=w.seed, iteration_counter=counter)
+    sl = gcp.SampledLoss(w.loss, X, M, cfg)
+    param = sl.parameter()
+    adam = gcp.Adam(M, lr=w.lr, lower=w.lower)
+
+    def step():
+        F = sl(param)
+        F.backward()
+        adam.step(param.grad.detach())
+        param.grad = None
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(args.steps):
+        step()
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / args.steps
+    print(f"[bench] autograd step (forward + MTTKRP backward + Adam): {ms * 1e3:.1f} us; "
+          f"plain fused step {plain_ms * 1e3:.1f} us", file=sys.stderr, flush=True)
+    return {"ms_per_step": ms, "value": w.n_samples / (ms / 1e3), "unit": "entries/s",
+            "plain_ms_per_step": plain_ms, "plain_over_autograd": ms / plain_ms,
+            "launch": "eager (forward, backward and Adam as separate calls)"}
 
 
 if __name__ == "__main__":

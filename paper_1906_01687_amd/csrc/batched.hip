@@ -57,6 +57,7 @@ struct BatchGradArgs {
     const uint8_t* lds_fp32;   // per problem: LDS partial held in FP32
     const uint64_t* iter_ctr;
     int64_t* adam_state;
+    uint32_t stage_off;  // byte offset of the per-wave sample records in the dynamic LDS
 };
 
 struct BatchReduceArgs {
@@ -89,6 +90,9 @@ template <int D, typename FT, typename VT>
 __global__ __launch_bounds__(1024) void batched_grad_kernel(BatchGradArgs ba) {
     using T = typename Compute<FT>::type;
     extern __shared__ double lds[];
+    // this wave's 64 sample records, after the largest partial
+    Sample<D, T>* const stage =
+        reinterpret_cast<Sample<D, T>*>(reinterpret_cast<char*>(lds) + ba.stage_off) + (threadIdx.x / kWave) * kWave;
     if (ba.adam_state && blockIdx.x == 0 && threadIdx.x == 0) ba.adam_state[0] += 1;
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t wib = threadIdx.x / kWave;
@@ -128,8 +132,8 @@ __global__ __launch_bounds__(1024) void batched_grad_kernel(BatchGradArgs ba) {
             // the next item's gathers are in flight while this one is evaluated
             Sample<D, T> nxt = item + nwib < un.item_end ? draw(item + nwib) : no_sample<D, T>();
             to_rows(a, cur);
-            if (f32) evaluate_and_scatter<D, FT, false, float>(a, reinterpret_cast<float*>(lds), cur, fsum);
-            else evaluate_and_scatter<D, FT, false, double>(a, lds, cur, fsum);
+            if (f32) evaluate_and_scatter<D, FT, false, float>(a, reinterpret_cast<float*>(lds), stage, cur, fsum);
+            else evaluate_and_scatter<D, FT, false, double>(a, lds, stage, cur, fsum);
             cur = nxt;
         }
         const int32_t next = u + 1 < u_end ? ba.units[u + 1].problem : -1;
@@ -219,6 +223,7 @@ struct gcp_batch {
     int threads = 1024;
     int64_t blocks = 1;
     size_t lds_bytes = 0;
+    uint32_t stage_off = 0;
     int64_t P_all = 0;
     // workspace layout
     size_t off_args = 0, off_units = 0, off_bptr = 0, off_f32 = 0, off_red = 0, off_flat = 0, off_acc = 0;
@@ -275,6 +280,9 @@ gcp_status batch_create(const gcp_problem* problems, int32_t count, const gcp_ba
     B->flat_off.resize(count + 1);
     int64_t flat = 0;
     int64_t lds_max = 0;
+    // the per-wave sample records sit after the partial; partials get the rest
+    const int64_t stage_bytes = (int64_t)threads * stage_record_bytes(d, fdt);
+    const int64_t budget = kLdsLimitBytes - stage_bytes - 4096;
     std::vector<double> item_cost(count);
     std::vector<int64_t> items(count);
     int64_t total_items = 0;
@@ -317,12 +325,12 @@ gcp_status batch_create(const gcp_problem* problems, int32_t count, const gcp_ba
         }
         const int64_t P = off;
         // LDS partial: FP64 if it fits, else FP32, else device atomics only
-        if (P * 8 <= kLdsBudgetBytes) {
+        if (P * 8 <= budget) {
             a.priv_mask = (1u << d) - 1u;
             a.lds_total = P;
             B->lds_fp32[b] = 0;
             lds_max = std::max(lds_max, P * 8);
-        } else if (P * 4 <= kLdsBudgetBytes) {
+        } else if (P * 4 <= budget) {
             a.priv_mask = (1u << d) - 1u;
             a.lds_total = P;
             B->lds_fp32[b] = 1;
@@ -354,9 +362,12 @@ gcp_status batch_create(const gcp_problem* problems, int32_t count, const gcp_ba
     }
     B->flat_off[count] = flat;
     B->P_all = flat;
-    B->lds_bytes = (size_t)lds_max;
+    const int64_t stage_off = (lds_max + 15) / 16 * 16;
+    B->stage_off = (uint32_t)stage_off;
+    B->lds_bytes = (size_t)(stage_off + stage_bytes);
+    for (int32_t b = 0; b < count; ++b) B->args[b].stage_off = (uint32_t)stage_off;
     // persistent grid: as many workgroups as fit at once
-    int per_cu = lds_max > 0 ? (int)((160 * 1024) / (lds_max + 1024)) : 4;
+    int per_cu = (int)(kLdsLimitBytes / ((int64_t)B->lds_bytes + 1024));
     per_cu = std::min(per_cu, 2048 / threads);
     per_cu = std::max(per_cu, 1);
     int64_t blocks = (int64_t)device_cu_count() * per_cu;
@@ -520,6 +531,7 @@ gcp_status batch_step(gcp_batch* B, const AdamParams* adam, uint64_t* iteration_
     ba.lds_fp32 = reinterpret_cast<const uint8_t*>(base + B->off_f32);
     ba.iter_ctr = iteration_counter;
     ba.adam_state = adam ? adam->state : nullptr;
+    ba.stage_off = B->stage_off;
     dispatch_d(B->d, [&](auto dc) { batched_grad_launch<decltype(dc)::value>(B, ba, s, e0, e1); });
     if (gcp_status st = check_launch("gcp_batched step (gradient)")) return st;
     BatchReduceArgs r{};

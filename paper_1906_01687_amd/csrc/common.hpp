@@ -80,6 +80,14 @@ int device_cu_count();
 
 // LDS bytes a gradient workgroup may use for privatised FP64 partials.
 constexpr int64_t kLdsBudgetBytes = 156 * 1024;
+constexpr int64_t kLdsLimitBytes = 160 * 1024;  // dynamic LDS of one workgroup on gfx950
+
+// Bytes of one staged sample record (row offsets of d modes, value, weight),
+// padded to 16 like the device struct.
+inline int64_t stage_record_bytes(int d, int fdtype) {
+    const int64_t raw = 4 * (int64_t)d + 2 * (fdtype == GCP_F64 ? 8 : 4);
+    return (raw + 15) / 16 * 16;
+}
 
 // How a gradient launch scatters: which modes are privatised in LDS (and
 // where), which use device atomics, and the launch shape.
@@ -90,6 +98,9 @@ struct ScatterPlan {
     uint32_t priv_mask;                 // bit k: mode k accumulated in LDS
     int64_t lds_off[GCP_MAX_D];         // offset of mode k in the LDS partial (elements)
     int64_t lds_total;                  // elements of one partial
+    int lds_elem;                       // bytes per LDS element: 8 (FP64) or 4 (FP32, CAS adds)
+    uint32_t stage_off;                 // byte offset of the per-wave sample records, or 0xFFFFFFFF
+    int64_t shm_bytes;                  // dynamic LDS of one gradient workgroup
     int64_t acc_off[GCP_MAX_D];         // offset of mode k in the FP64 atomic accumulator
     int64_t acc_total;
     int64_t blocks;                     // gradient workgroups (= number of partials)

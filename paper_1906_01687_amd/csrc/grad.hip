@@ -33,6 +33,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <mutex>
 #include <unordered_set>
 
@@ -128,10 +129,15 @@ __device__ __forceinline__ Sample<D, typename Compute<FT>::type> item_sample(con
     return smp;
 }
 
-template <int D, typename FT, typename VT, bool LIST>
+template <int D, typename FT, typename VT, bool LIST, typename LT>
 __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
     using T = typename Compute<FT>::type;
-    extern __shared__ double lds[];
+    extern __shared__ double lds_raw[];
+    LT* const lds = reinterpret_cast<LT*>(lds_raw);
+    // this wave's 64 sample records (only used when a.stage_off != kNoStage)
+    Sample<D, T>* const stage = reinterpret_cast<Sample<D, T>*>(
+                                    reinterpret_cast<char*>(lds_raw) + (a.stage_off == kNoStage ? 0u : a.stage_off)) +
+                                (threadIdx.x / kWave) * kWave;
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t nthreads = blockDim.x;
     // nothing in this kernel reads the step count; the reduction after it does
@@ -147,9 +153,11 @@ __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
     // the clear runs under their latency
     Sample<D, T> cur = wave < n_items ? item_sample<D, FT, VT, LIST>(a, iter, wave) : no_sample<D, T>();
     {
-        double2* l2 = reinterpret_cast<double2*>(lds);
-        for (int64_t e = threadIdx.x; e < a.lds_total / 2; e += nthreads) l2[e] = double2{0.0, 0.0};
-        if ((a.lds_total & 1) && threadIdx.x == 0) lds[a.lds_total - 1] = 0.0;
+        constexpr int per16 = 16 / sizeof(LT);
+        uint4* l16 = reinterpret_cast<uint4*>(lds_raw);
+        const int64_t n16 = a.lds_total / per16;
+        for (int64_t e = threadIdx.x; e < n16; e += nthreads) l16[e] = uint4{0u, 0u, 0u, 0u};
+        for (int64_t e = n16 * per16 + threadIdx.x; e < a.lds_total; e += nthreads) lds[e] = LT(0);
     }
     __syncthreads();
 
@@ -158,7 +166,7 @@ __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
         const int64_t next = item + nwave;
         Sample<D, T> nxt = next < n_items ? item_sample<D, FT, VT, LIST>(a, iter, next) : no_sample<D, T>();
         to_rows(a, cur);
-        evaluate_and_scatter<D, FT, LIST>(a, lds, cur, fsum);
+        evaluate_and_scatter<D, FT, LIST>(a, lds, stage, cur, fsum);
         if constexpr (!LIST) {
             if (a.n_zero_items > 0 && item == n_items - 1) {
                 // the last zero chunk, and the first batch held fewer than q
@@ -174,7 +182,7 @@ __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
                     const int cz = (ok && rk < (uint64_t)a.q) ? GCP_STRATUM_ZERO : -1;
                     Sample<D, T> z = make_sample<D, T>(a, i, T(0), cz);
                     to_rows(a, z);
-                    evaluate_and_scatter<D, FT, false>(a, lds, z, fsum);
+                    evaluate_and_scatter<D, FT, false>(a, lds, stage, z, fsum);
                     filled += __popcll(b2);
                     base += kWave;
                 }
@@ -193,15 +201,23 @@ __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
     // one dense partial per workgroup, plain stores (FP32 unless the factors are FP64)
     using PT = typename Partial<FT>::type;
     PT* __restrict__ part = static_cast<PT*>(a.partials) + (int64_t)blockIdx.x * a.lds_total;
-    constexpr int kVec = 16 / sizeof(PT);  // elements per 16-byte store
-    if (a.lds_total % kVec == 0) {
-        for (int64_t e = threadIdx.x; e < a.lds_total / kVec; e += nthreads) {
-            if constexpr (kVec == 4) {
-                const double2 u = reinterpret_cast<const double2*>(lds)[2 * e];
-                const double2 v = reinterpret_cast<const double2*>(lds)[2 * e + 1];
-                reinterpret_cast<float4*>(part)[e] = float4{(float)u.x, (float)u.y, (float)v.x, (float)v.y};
+    if (a.lds_total % 4 == 0) {
+        // four elements per step: 16-byte LDS reads, 16-byte (FP32) or 2 x 16-byte (FP64) stores
+        for (int64_t e = threadIdx.x; e < a.lds_total / 4; e += nthreads) {
+            LT v[4];
+            if constexpr (sizeof(LT) == 8) {
+                const double2 u = reinterpret_cast<const double2*>(lds_raw)[2 * e];
+                const double2 w = reinterpret_cast<const double2*>(lds_raw)[2 * e + 1];
+                v[0] = (LT)u.x, v[1] = (LT)u.y, v[2] = (LT)w.x, v[3] = (LT)w.y;
             } else {
-                reinterpret_cast<double2*>(part)[e] = reinterpret_cast<const double2*>(lds)[e];
+                const float4 u = reinterpret_cast<const float4*>(lds_raw)[e];
+                v[0] = (LT)u.x, v[1] = (LT)u.y, v[2] = (LT)u.z, v[3] = (LT)u.w;
+            }
+            if constexpr (sizeof(PT) == 4) {
+                reinterpret_cast<float4*>(part)[e] = float4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+            } else {
+                reinterpret_cast<double2*>(part)[2 * e] = double2{(double)v[0], (double)v[1]};
+                reinterpret_cast<double2*>(part)[2 * e + 1] = double2{(double)v[2], (double)v[3]};
             }
         }
     } else {
@@ -210,13 +226,19 @@ __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Unfused derivative: one thread per sample reads its indices, value and
-// stratum, forms m_i and writes ytilde_i (gcp_loss_grad).
+// Unfused derivative (gcp_loss_grad).  Same lane layout as the fused kernel:
+// lane l of a wave reads sample l of its 64-sample item (indices, value,
+// stratum) and stores its record in the wave's LDS slice; in each pass a
+// group of lps lanes reads one record, gathers the sample's rows (coalesced),
+// forms m with a VALU group sum, and lane 0 of the group writes ytilde and
+// adds its weighted loss.
 // ---------------------------------------------------------------------------
 struct LossArgs {
     int loss;
     int r;
+    int lps;
     int64_t S;
+    int64_t n[GCP_MAX_D];
     const uint32_t* idx;
     const void* xval;
     const uint8_t* stratum;
@@ -227,40 +249,98 @@ struct LossArgs {
     double* loss_sum;
 };
 
+template <int NB, int D, typename FT>
+__device__ __forceinline__ void loss_passes(const LossArgs& a, const __amdgpu_buffer_rsrc_t (&rs)[D], int64_t item,
+                                            const Sample<D, typename Compute<FT>::type>* stage,
+                                            typename Compute<FT>::type& fsum) {
+    using T = typename Compute<FT>::type;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int lps = a.lps, spw = kWave / lps, slot = lane / lps;
+    const uint32_t j = (uint32_t)(lane & (lps - 1));
+    const bool colj = (int)j < a.r;
+    const T eps = (T)a.eps;
+    for (int p0 = 0; p0 < lps; p0 += NB) {
+        uint32_t qq[NB][D];
+        T xx[NB], ww[NB];
+        int src[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            src[u] = (p0 + u < lps ? p0 + u : 0) * spw + slot;
+            const Sample<D, T> rec = stage[src[u]];   // broadcast read of the group's record
+#pragma unroll
+            for (int k = 0; k < D; ++k) qq[u][k] = rec.q[k];
+            xx[u] = rec.x;
+            ww[u] = rec.w;
+        }
+        T prod[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            prod[u] = T(1);
+#pragma unroll
+            for (int k = 0; k < D; ++k) prod[u] *= RowLoad<FT>::at(rs[k], qq[u][k] + j);
+            prod[u] = colj ? prod[u] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const T m = group_sum(prod[u], lps);
+            const int64_t cs = item * kWave + src[u];
+            if (j == 0 && p0 + u < lps && cs < a.S) {
+                static_cast<T*>(a.ytilde)[cs] = weighted_g(a.loss, xx[u], m, ww[u], eps);
+                if (a.loss_sum) {
+                    const bool corr = ww[u] < T(0);
+                    T f = loss_f<T>(a.loss, xx[u], m, eps);
+                    if (corr) f -= loss_f<T>(a.loss, T(0), m, eps);
+                    fsum += (corr ? -ww[u] : ww[u]) * f;
+                }
+            }
+        }
+    }
+}
+
 template <int D, typename FT, typename VT>
 __global__ __launch_bounds__(256) void loss_grad_kernel(LossArgs a) {
     using T = typename Compute<FT>::type;
-    const int r = a.r;
-    const T eps = (T)a.eps;
-    double fsum = 0.0;
-    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < a.S;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t i[D];
+    const int lane = threadIdx.x & (kWave - 1);
+    __amdgpu_buffer_rsrc_t rs[D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) i[k] = a.idx[c * D + k];
-        T m = T(0);
-        for (int jj = 0; jj < r; ++jj) {
-            T prod = T(1);
+    for (int k = 0; k < D; ++k) {
+        const uint64_t bytes = (uint64_t)a.n[k] * (uint64_t)a.r * sizeof(FT);
+        rs[k] = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(a.A[k]), (short)0,
+                                                  (int)(bytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)bytes),
+                                                  kBufferWord3);
+    }
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    const int64_t items = (a.S + kWave - 1) / kWave;
+    __shared__ Sample<D, T> stage_all[4][kWave];   // 256 threads: 4 waves
+    Sample<D, T>* const stage = stage_all[threadIdx.x / kWave];
+    T fsum = T(0);
+    for (int64_t item = wave; item < items; item += nwave) {
+        const int64_t c = item * kWave + lane;
+        Sample<D, T> smp = no_sample<D, T>();
+        if (c < a.S) {
 #pragma unroll
-            for (int k = 0; k < D; ++k) prod *= widen(static_cast<const FT*>(a.A[k])[(size_t)i[k] * r + jj]);
-            m += prod;
+            for (int k = 0; k < D; ++k) smp.q[k] = a.idx[c * D + k] * (uint32_t)a.r;
+            const int code = a.stratum[c];
+            smp.x = (T) static_cast<const VT*>(a.xval)[c];
+            const T wt = pick_weight<T>(a.w, code);
+            smp.w = code == GCP_STRATUM_NZ_CORR ? -wt : wt;
         }
-        const int code = a.stratum[c];
-        const T w = pick_weight<T>(a.w, code);
-        const T x = (T) static_cast<const VT*>(a.xval)[c];
-        const bool corr = code == GCP_STRATUM_NZ_CORR;
-        T g = loss_g<T>(a.loss, x, m, eps);
-        if (corr) g -= loss_g<T>(a.loss, T(0), m, eps);
-        static_cast<T*>(a.ytilde)[c] = w * g;
-        if (a.loss_sum) {
-            T f = loss_f<T>(a.loss, x, m, eps);
-            if (corr) f -= loss_f<T>(a.loss, T(0), m, eps);
-            fsum += (double)(w * f);
+        // this wave's slice; its ds operations complete in order
+        stage[lane] = smp;
+        constexpr int words = D + (2 + D) * (int)(sizeof(T) / 4);
+        constexpr int nb = words * 8 <= 64 ? 8 : (words * 4 <= 64 ? 4 : 2);
+        if constexpr (nb == 8) {
+            if (a.lps <= 4) loss_passes<4, D, FT>(a, rs, item, stage, fsum);
+            else loss_passes<8, D, FT>(a, rs, item, stage, fsum);
+        } else {
+            loss_passes<nb, D, FT>(a, rs, item, stage, fsum);
         }
     }
     if (a.loss_sum) {
-        for (int o = kWave / 2; o > 0; o >>= 1) fsum += __shfl_xor(fsum, o);
-        if ((threadIdx.x & (kWave - 1)) == 0 && fsum != 0.0) unsafeAtomicAdd(a.loss_sum, fsum);
+        double f = (double)fsum;
+        for (int o = kWave / 2; o > 0; o >>= 1) f += __shfl_xor(f, o);
+        if (lane == 0 && f != 0.0) unsafeAtomicAdd(a.loss_sum, f);
     }
 }
 
@@ -457,7 +537,9 @@ ScatterPlan plan_scatter(const gcp_tensor* X, const gcp_factors* M, int64_t n_it
     }
     for (int k = X->d; k <= GCP_MAX_D; ++k) pl.off[k] = off;
     pl.P = off;
-    // privatise the shortest modes first while their FP64 partials fit in LDS
+    // privatise the shortest modes first while their partials fit in LDS: in
+    // FP64, or for FP32/BF16 factors in FP32 when that holds more of the
+    // gradient (FP32 partials are added with compare-and-swap)
     int order[GCP_MAX_D];
     for (int k = 0; k < X->d; ++k) order[k] = k;
     for (int a = 0; a < X->d; ++a)
@@ -467,17 +549,31 @@ ScatterPlan plan_scatter(const gcp_tensor* X, const gcp_factors* M, int64_t n_it
                 order[a] = order[b];
                 order[b] = t;
             }
-    const int64_t budget = kLdsBudgetBytes / 8;
-    int64_t lds = 0, acc = 0;
-    for (int a = 0; a < X->d; ++a) {
-        const int k = order[a];
-        const int64_t n = X->dims[k] * r;
-        if (lds + n <= budget) {
-            pl.priv_mask |= 1u << k;
-            pl.lds_off[k] = lds;
-            lds += n;
+    auto privatise = [&](int elem, uint32_t* mask, int64_t* offs) {
+        const int64_t budget = kLdsBudgetBytes / elem;
+        int64_t lds = 0;
+        *mask = 0;
+        for (int a = 0; a < X->d; ++a) {
+            const int k = order[a];
+            const int64_t n = X->dims[k] * r;
+            if (lds + n <= budget) {
+                *mask |= 1u << k;
+                offs[k] = lds;
+                lds += n;
+            }
         }
-    }
+        return lds;
+    };
+    int64_t offs64[GCP_MAX_D] = {0}, offs32[GCP_MAX_D] = {0};
+    uint32_t mask64 = 0, mask32 = 0;
+    const int64_t n64 = privatise(8, &mask64, offs64);
+    const int64_t n32 = M->dtype == GCP_F64 ? 0 : privatise(4, &mask32, offs32);
+    const bool use32 = n32 > n64;
+    pl.priv_mask = use32 ? mask32 : mask64;
+    pl.lds_elem = use32 ? 4 : 8;
+    const int64_t lds = use32 ? n32 : n64;
+    for (int k = 0; k < X->d; ++k) pl.lds_off[k] = use32 ? offs32[k] : offs64[k];
+    int64_t acc = 0;
     for (int k = 0; k < X->d; ++k)
         if (!((pl.priv_mask >> k) & 1u)) {
             pl.acc_off[k] = acc;
@@ -486,9 +582,18 @@ ScatterPlan plan_scatter(const gcp_tensor* X, const gcp_factors* M, int64_t n_it
     pl.lds_total = lds;
     pl.acc_total = acc;
     // launch shape: big LDS footprints get one 1024-thread workgroup per CU
-    const int64_t lds_bytes = lds * 8;
+    const int64_t lds_bytes = (lds * pl.lds_elem + 15) / 16 * 16;
     pl.threads = lds_bytes > 40 * 1024 ? 1024 : 512;
-    int per_cu = lds_bytes > 0 ? (int)((160 * 1024) / (lds_bytes + 1024)) : 4;
+    // per-wave sample records for phase B when they fit beside the partial
+    const int64_t stage_bytes = (int64_t)pl.threads * stage_record_bytes(X->d, M->dtype);
+    if (lds_bytes + stage_bytes <= kLdsLimitBytes) {
+        pl.stage_off = (uint32_t)lds_bytes;
+        pl.shm_bytes = lds_bytes + stage_bytes;
+    } else {
+        pl.stage_off = kNoStage;
+        pl.shm_bytes = lds_bytes;
+    }
+    int per_cu = pl.shm_bytes > 0 ? (int)(kLdsLimitBytes / (pl.shm_bytes + 1024)) : 4;
     const int max_per_cu = 2048 / pl.threads;
     if (per_cu > max_per_cu) per_cu = max_per_cu;
     if (per_cu < 1) per_cu = 1;
@@ -509,7 +614,7 @@ template <int D, bool LIST>
 static void grad_launch(const GradArgs& a, const ScatterPlan& pl, int fdtype, int vdtype, hipStream_t s,
                         hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr) {
     const dim3 g((unsigned)pl.blocks), b((unsigned)pl.threads);
-    const size_t shm = (size_t)pl.lds_total * 8;
+    const size_t shm = (size_t)pl.shm_bytes;
     auto go = [&](auto kernel) {
         allow_full_lds(reinterpret_cast<const void*>(kernel));
         if (ev_start || ev_stop)
@@ -517,15 +622,26 @@ static void grad_launch(const GradArgs& a, const ScatterPlan& pl, int fdtype, in
         else
             hipLaunchKernelGGL(kernel, g, b, shm, s, a);
     };
+    const bool f32 = pl.lds_elem == 4;
     if (fdtype == GCP_F64) {
-        if (vdtype == GCP_F64) go(grad_kernel<D, double, double, LIST>);
-        else go(grad_kernel<D, double, float, LIST>);
+        if (vdtype == GCP_F64) go(grad_kernel<D, double, double, LIST, double>);
+        else go(grad_kernel<D, double, float, LIST, double>);
     } else if (fdtype == GCP_F32) {
-        if (vdtype == GCP_F64) go(grad_kernel<D, float, double, LIST>);
-        else go(grad_kernel<D, float, float, LIST>);
+        if (vdtype == GCP_F64) {
+            if (f32) go(grad_kernel<D, float, double, LIST, float>);
+            else go(grad_kernel<D, float, double, LIST, double>);
+        } else {
+            if (f32) go(grad_kernel<D, float, float, LIST, float>);
+            else go(grad_kernel<D, float, float, LIST, double>);
+        }
     } else {
-        if (vdtype == GCP_F64) go(grad_kernel<D, bf16_t, double, LIST>);
-        else go(grad_kernel<D, bf16_t, float, LIST>);
+        if (vdtype == GCP_F64) {
+            if (f32) go(grad_kernel<D, bf16_t, double, LIST, float>);
+            else go(grad_kernel<D, bf16_t, double, LIST, double>);
+        } else {
+            if (f32) go(grad_kernel<D, bf16_t, float, LIST, float>);
+            else go(grad_kernel<D, bf16_t, float, LIST, double>);
+        }
     }
 }
 
@@ -552,6 +668,7 @@ static GradArgs base_args(const gcp_tensor* X, const gcp_factors* M, const Scatt
     }
     a.priv_mask = pl.priv_mask;
     a.lds_total = pl.lds_total;
+    a.stage_off = pl.stage_off;
     a.acc = acc;
     a.partials = partials;
     return a;
@@ -675,7 +792,10 @@ gcp_status launch_reduce(const gcp_factors* M, const ScatterPlan& pl, const doub
 
 template <int D>
 static void loss_launch(const LossArgs& a, int fdtype, int vdtype, hipStream_t s) {
-    const dim3 g(grid_cap(a.S, 256, 4096)), b(256);
+    // 4 waves per workgroup, one 64-sample item per wave and turn
+    const int64_t items = (a.S + kWave - 1) / kWave;
+    const dim3 g((unsigned)std::max<int64_t>(1, std::min<int64_t>((items + 3) / 4, (int64_t)device_cu_count() * 8))),
+        b(256);
     if (fdtype == GCP_F64) {
         if (vdtype == GCP_F64) hipLaunchKernelGGL((loss_grad_kernel<D, double, double>), g, b, 0, s, a);
         else hipLaunchKernelGGL((loss_grad_kernel<D, double, float>), g, b, 0, s, a);
@@ -695,7 +815,9 @@ gcp_status launch_loss_grad(gcp_loss loss, const gcp_tensor* X, const gcp_sampli
     LossArgs a{};
     a.loss = loss;
     a.r = (int)M->rank;
+    a.lps = lanes_per_sample(M->rank);
     a.S = S;
+    for (int k = 0; k < X->d; ++k) a.n[k] = X->dims[k];
     a.idx = idx;
     a.xval = xval;
     a.stratum = stratum;

@@ -45,7 +45,12 @@ struct GradArgs {
     double eps;
     double* loss_sum;
     int64_t* adam_state;  // fused step: state[0] += 1 here, read by the reduction
+    // byte offset in the dynamic LDS of the per-wave sample records (64 per
+    // wave, in wave order), or kNoStage when phase B broadcasts with ds_bpermute
+    uint32_t stage_off;
 };
+
+constexpr uint32_t kNoStage = 0xFFFFFFFFu;
 
 
 // Partial-gradient storage: FP64 for FP64 factors, FP32 otherwise.
@@ -114,7 +119,7 @@ __device__ __forceinline__ void lds_add(float* p, float v) {
 // row offsets once they are needed, so a prefetched sample's gathers overlap
 // the evaluation of the previous one.
 template <int D, typename T>
-struct Sample {
+struct alignas(16) Sample {
     uint32_t q[D];  // i_k from phase A; i_k * r after to_rows()
     T x;            // data value (list mode: ytilde)
     T w;            // stratum weight, negated for a corrected nonzero (g(x,m) - g(0,m)); 0: no sample
@@ -281,8 +286,9 @@ struct PhaseB {
     double* accj[D];
 };
 
-template <int NB, int D, typename FT, bool LIST, typename LT>
+template <int NB, int D, typename FT, bool LIST, typename LT, bool STAGED>
 __device__ __forceinline__ void pass_batches(const GradArgs& a, const PhaseB<D, LT>& b, LT* __restrict__ lds,
+                                             const Sample<D, typename Compute<FT>::type>* stage,
                                              const Sample<D, typename Compute<FT>::type>& smp,
                                              typename Compute<FT>::type& fsum) {
     using T = typename Compute<FT>::type;
@@ -293,11 +299,21 @@ __device__ __forceinline__ void pass_batches(const GradArgs& a, const PhaseB<D, 
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
             const bool pass_ok = p0 + u < b.lps;
-            const int addr = ((pass_ok ? p0 + u : 0) * b.spw + b.slot) << 2;
+            const int src = (pass_ok ? p0 + u : 0) * b.spw + b.slot;
+            T wv;
+            if constexpr (STAGED) {
+                // one record per lane group: 16-byte broadcast reads
+                const Sample<D, T> rec = stage[src];
 #pragma unroll
-            for (int k = 0; k < D; ++k) qq[u][k] = bcast(smp.q[k], addr);
-            xx[u] = bcast(smp.x, addr);
-            const T wv = bcast(smp.w, addr);
+                for (int k = 0; k < D; ++k) qq[u][k] = rec.q[k];
+                xx[u] = rec.x;
+                wv = rec.w;
+            } else {
+#pragma unroll
+                for (int k = 0; k < D; ++k) qq[u][k] = bcast(smp.q[k], src << 2);
+                xx[u] = bcast(smp.x, src << 2);
+                wv = bcast(smp.w, src << 2);
+            }
             ww[u] = pass_ok ? wv : T(0);
         }
         T av[NB][D];
@@ -351,12 +367,16 @@ __device__ __forceinline__ void pass_batches(const GradArgs& a, const PhaseB<D, 
 // Phase B: the wave's 64 samples (one per lane in smp, rows already formed by
 // to_rows) are evaluated and scattered into the LDS partial (accumulator type
 // LT) for privatised modes and into a.acc with device atomics for the others.
+// With a staging slice (64 records of this wave in LDS), each pass reads its
+// sample's record with wide broadcast reads; without one it broadcasts with
+// ds_bpermute (about six times the LDS time per word, measured).
 // A sample takes a group of lps lanes, lane j holding column j of its rows, so
 // one pass covers 64/lps samples.  Passes are taken 2 to 8 at a time so that
 // the row gathers of a batch are all in flight before any of them is
 // consumed.  Every lane of the wave must call this.
 template <int D, typename FT, bool LIST, typename LT = double>
 __device__ __forceinline__ void evaluate_and_scatter(const GradArgs& a, LT* __restrict__ lds,
+                                                     Sample<D, typename Compute<FT>::type>* stage,
                                                      const Sample<D, typename Compute<FT>::type>& smp,
                                                      typename Compute<FT>::type& fsum) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -384,11 +404,24 @@ __device__ __forceinline__ void evaluate_and_scatter(const GradArgs& a, LT* __re
     using T = typename Compute<FT>::type;
     constexpr int words = D + (2 + D) * (int)(sizeof(T) / 4);
     constexpr int nb = words * 8 <= 64 ? 8 : (words * 4 <= 64 ? 4 : 2);
-    if constexpr (nb == 8) {
-        if (b.lps <= 4) pass_batches<4, D, FT, LIST, LT>(a, b, lds, smp, fsum);
-        else pass_batches<8, D, FT, LIST, LT>(a, b, lds, smp, fsum);
+    if (uni(a.stage_off) != kNoStage) {
+        // the wave's own slice: ds operations of one wave complete in order, so
+        // the reads below see these writes and the next item's writes cannot
+        // overtake them
+        stage[lane] = smp;
+        if constexpr (nb == 8) {
+            if (b.lps <= 4) pass_batches<4, D, FT, LIST, LT, true>(a, b, lds, stage, smp, fsum);
+            else pass_batches<8, D, FT, LIST, LT, true>(a, b, lds, stage, smp, fsum);
+        } else {
+            pass_batches<nb, D, FT, LIST, LT, true>(a, b, lds, stage, smp, fsum);
+        }
     } else {
-        pass_batches<nb, D, FT, LIST, LT>(a, b, lds, smp, fsum);
+        if constexpr (nb == 8) {
+            if (b.lps <= 4) pass_batches<4, D, FT, LIST, LT, false>(a, b, lds, stage, smp, fsum);
+            else pass_batches<8, D, FT, LIST, LT, false>(a, b, lds, stage, smp, fsum);
+        } else {
+            pass_batches<nb, D, FT, LIST, LT, false>(a, b, lds, stage, smp, fsum);
+        }
     }
 }
 

@@ -21,8 +21,15 @@ Workloads (dims, rank, loss, sampler; data recipe):
   sum(1 - exp(-lambda*m)) is 5e6; entries are Poisson(lambda*m).  Poisson loss,
   semi-stratified sampling p = q = 5e5.  Stands in for the Chicago crime
   tensor (6186x24x77x32, 5.3M nonzeros, rank 10), which is not available.
+* ``dense_gaussian_200x200x200x200`` -- 200^4, rank 32, FP32 data (6.4 GB,
+  generated in slabs).  X = [[A1..A4]] with N(0,1) factor entries plus
+  0.1*N(0,1) noise; Gaussian loss; uniform sampling, s = 1e6; factors stored
+  in FP32 or BF16 (``_bf16``); evaluated at an independent N(0,1) start.
+* ``batch_of_cubes`` -- 64 dense cubes, sides round(exp(U(ln 20, ln 300))),
+  ranks uniform over {4, 8, 16, 32}, losses b mod 3 with the data of the
+  recipes above, s = ceil(2% of the entries) uniform samples each.
 
-Seeds: data 1000c+1, start 1000c+2, samples 1000c+3 for workload c = 1, 2, 3.
+Seeds: data 1000c+1, start 1000c+2, samples 1000c+3 for workload c = 1..4.
 """
 from __future__ import annotations
 
@@ -282,6 +289,35 @@ def sparse_count_workload(dims=(6000, 24, 77, 32), rank=10, nnz_target=5.0e6, p=
                     A_true=A_true, A_init=A0, seed=seed_base + 3, lower=0.0)
 
 
+def dense_gaussian_4way_f32(dims=(200, 200, 200, 200), rank=32, noise=0.1, seed=4001, chunk_rows=1000):
+    """FP32 X = [[A_1..A_4]] + noise*N(0,1) with N(0,1) factors, generated in
+    slabs of the (n_1 n_2) x (n_3 n_4) matricization: the model part as a
+    float64 product of Khatri-Rao factors rounded to float32, the noise from
+    one sequential float32 normal stream.  Returns (X, A_true)."""
+    assert len(dims) == 4
+    rng = np.random.Generator(np.random.PCG64(seed))
+    A = [rng.standard_normal((n, rank)) for n in dims]
+    left = (A[0][:, None, :] * A[1][None, :, :]).reshape(dims[0] * dims[1], rank)
+    right = (A[2][:, None, :] * A[3][None, :, :]).reshape(dims[2] * dims[3], rank)
+    X = np.empty((dims[0] * dims[1], dims[2] * dims[3]), dtype=np.float32)
+    for r0 in range(0, X.shape[0], chunk_rows):
+        r1 = min(r0 + chunk_rows, X.shape[0])
+        X[r0:r1] = left[r0:r1] @ right.T
+        X[r0:r1] += np.float32(noise) * rng.standard_normal((r1 - r0, X.shape[1]), dtype=np.float32)
+    return X.reshape(dims), A
+
+
+def dense_gaussian_200x200x200x200(dtype="f32", s=1_000_000) -> Workload:
+    """200^4 Gaussian, rank 32, FP32 data (6.4 GB), uniform s = 1e6; factors in
+    FP32 or BF16 storage (BF16: FP32 master, BF16 copy for the gathers)."""
+    dims, r = (200, 200, 200, 200), 32
+    X, A_true = dense_gaussian_4way_f32(dims, r, seed=4001)
+    A0 = gaussian_start(dims, r, seed=4002)
+    name = "dense_gaussian_200x200x200x200" + ("_bf16" if dtype == "bf16" else "")
+    return Workload(name, dims, r, GAUSSIAN, UNIFORM, dtype, s=s, dense=X, A_true=A_true, A_init=A0,
+                    seed=4003, lr=1e-3)
+
+
 def sparse_binary_1000x800x600() -> Workload:
     return sparse_binary_workload()
 
@@ -294,6 +330,8 @@ WORKLOADS = {
     "dense_gaussian_30x40x50": dense_gaussian_30x40x50,
     "sparse_binary_1000x800x600": sparse_binary_1000x800x600,
     "sparse_count_6000x24x77x32": sparse_count_6000x24x77x32,
+    "dense_gaussian_200x200x200x200": dense_gaussian_200x200x200x200,
+    "dense_gaussian_200x200x200x200_bf16": lambda: dense_gaussian_200x200x200x200("bf16"),
 }
 
 

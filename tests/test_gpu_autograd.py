@@ -1,0 +1,194 @@
+"""GPU checks of the differentiable sampled loss (paper_1906_01687_amd.autograd).
+
+The forward must return the oracle's loss estimate and the backward the
+oracle's sampled gradient on the same samples (1e-12 relative in FP64, 1e-5
+in FP32 and BF16 storage, the oracle seeing the stored values).  Finite
+differences of the loss (h = 1e-3, FP64) pin the backward to the forward: for
+the Gaussian loss F is quadratic along one coordinate (m is linear in each
+factor entry), so central differences are exact up to rounding.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+import paper_1906_01687_amd as gcp
+from gpu_cases import (cfg_for, host_rounded, oracle_grad, oracle_samples, rel_fro, small_dense, small_sparse,
+                       to_device)
+
+pytestmark = pytest.mark.gpu
+TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 1e-5}
+
+
+def announce(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+CASES = [
+    ("dense_f64_gauss", lambda: synth.dense_gaussian_30x40x50(), "f64"),
+    ("dense_f32_poisson", lambda: small_dense(rank=10, loss=synth.POISSON), "f32"),
+    ("dense_bf16_gauss_r32", lambda: small_dense(dims=(23, 19, 17, 9), rank=32, s=4000), "bf16"),
+    ("binary_strat_f32", lambda: small_sparse("binary"), "f32"),
+    ("counts_semi_f32", lambda: small_sparse("counts", rank=10), "f32"),
+]
+
+
+@pytest.mark.parametrize("name,make,dtype", CASES, ids=[c[0] for c in CASES])
+def test_forward_and_backward_match_oracle(name, make, dtype):
+    announce(f"autograd forward/backward vs oracle {name}")
+    w = make()
+    pb = to_device(w, dtype=dtype)
+    cfg = cfg_for(pb, iteration=5)
+    sl = gcp.SampledLoss(w.loss, pb.X, pb.M, cfg)
+    p = sl.parameter()
+    F = sl(p)
+    F.backward()
+    smp = oracle_samples(pb, iteration=5)
+    Gref, Fref, _ = oracle_grad(pb, smp)
+    torch.cuda.synchronize()
+    tol = TOL[dtype]
+    assert abs(F.item() - Fref) <= 10 * tol * max(1.0, abs(Fref)), (F.item(), Fref)
+    assert p.grad.dtype == (torch.float64 if dtype == "f64" else torch.float32)
+    errs = rel_fro(pb.M.grad_views(p.grad), Gref)
+    assert max(errs) <= tol, errs
+    p.grad = None
+
+
+def test_backward_scales_by_incoming_gradient():
+    announce("autograd chain rule: d(3F)/dA = 3 dF/dA")
+    w = small_dense(dtype="f64", loss=synth.POISSON)
+    pb = to_device(w, dtype="f64")
+    sl = gcp.SampledLoss(w.loss, pb.X, pb.M, cfg_for(pb, iteration=1))
+    p = sl.parameter()
+    sl(p).backward()
+    g1 = p.grad.clone()
+    p.grad = None
+    (3.0 * sl(p)).backward()
+    torch.cuda.synchronize()
+    torch.testing.assert_close(p.grad, 3.0 * g1, rtol=1e-13, atol=0.0)
+
+
+def _oracle_loss(pb, smp, A):
+    _, F = oracle.grad(pb.w.loss, pb.w.dims, A, smp, nnz=pb.w.nnz, s=pb.w.s, p=pb.w.p, q=pb.w.q)
+    return F
+
+
+@pytest.mark.parametrize("loss", [synth.GAUSSIAN, synth.POISSON])
+def test_finite_differences(loss):
+    """Central differences (h = 1e-3) of the FP64 oracle loss on fixed samples
+    against the GPU backward, coordinate by coordinate and along random
+    directions."""
+    announce(f"finite differences h=1e-3, loss {loss}")
+    if loss == synth.GAUSSIAN:
+        w = synth.dense_gaussian_30x40x50()
+    else:
+        w = small_dense(dims=(9, 8, 7), rank=3, s=600, dtype="f64", loss=synth.POISSON)
+    pb = to_device(w, dtype="f64")
+    sl = gcp.SampledLoss(w.loss, pb.X, pb.M, cfg_for(pb, iteration=2))
+    p = sl.parameter()
+    sl(p).backward()
+    G = [g.detach().cpu().numpy() for g in pb.M.grad_views(p.grad)]
+    smp = oracle_samples(pb, iteration=2)
+    A = [a.copy() for a in pb.A64]
+    h = 1e-3
+    rng = np.random.default_rng(17)
+    gscale = max(float(np.abs(g).max()) for g in G)
+    for _ in range(12):
+        k = int(rng.integers(0, w.d))
+        i = int(rng.integers(0, w.dims[k]))
+        j = int(rng.integers(0, w.rank))
+        Ap = [a.copy() for a in A]
+        Am = [a.copy() for a in A]
+        Ap[k][i, j] += h
+        Am[k][i, j] -= h
+        fd = (_oracle_loss(pb, smp, Ap) - _oracle_loss(pb, smp, Am)) / (2 * h)
+        # Gaussian: exact up to rounding; Poisson: O(h^2)
+        tol = 1e-7 * gscale if loss == synth.GAUSSIAN else 1e-4 * max(abs(fd), 1e-3 * gscale)
+        assert abs(fd - G[k][i, j]) <= tol, (k, i, j, fd, G[k][i, j])
+    # along a random direction m is a polynomial of degree d in the step, so
+    # the central difference is off by O(h^2): it must shrink ~4x when h halves
+    for _ in range(3):
+        V = [rng.standard_normal(a.shape) for a in A]
+        dd = sum(float((g * v).sum()) for g, v in zip(G, V))
+        errs = []
+        for hh in (h, h / 2):
+            Ap = [a + hh * v for a, v in zip(A, V)]
+            Am = [a - hh * v for a, v in zip(A, V)]
+            errs.append(abs((_oracle_loss(pb, smp, Ap) - _oracle_loss(pb, smp, Am)) / (2 * hh) - dd))
+        assert errs[0] <= 1e-4 * max(1.0, abs(dd)), (errs, dd)
+        assert errs[1] <= 0.3 * errs[0] + 1e-9 * max(1.0, abs(dd)), (errs, dd)
+    p.grad = None
+
+
+def test_torch_gradcheck_fp64():
+    announce("torch.autograd.gradcheck, FP64, 3 x 4 x 5 Bernoulli-odds")
+    w = small_dense(dims=(3, 4, 5), rank=2, s=60, dtype="f64", loss=synth.BERNOULLI_ODDS)
+    pb = to_device(w, dtype="f64")
+    sl = gcp.SampledLoss(w.loss, pb.X, pb.M, cfg_for(pb, iteration=0))
+    p = pb.M.flat.detach().clone().requires_grad_(True)
+
+    def f(param):
+        pb.M.flat.copy_(param.detach())   # the kernels read the Factors storage
+        return sl(param)
+
+    assert torch.autograd.gradcheck(f, (p,), eps=1e-6, atol=1e-6, rtol=1e-4)
+
+
+def test_counter_draws_fresh_samples():
+    announce("autograd with the device iteration counter")
+    w = small_sparse("binary")
+    pb = to_device(w)
+    counter = torch.zeros(1, dtype=torch.int64, device="cuda")
+    cfg = gcp.sampling("stratified", p=w.p, q=w.q, seed=w.seed, iteration=3, iteration_counter=counter)
+    sl = gcp.SampledLoss(w.loss, pb.X, pb.M, cfg)
+    p = sl.parameter()
+    F0 = sl(p)
+    F1 = sl(p)
+    F1.backward()
+    torch.cuda.synchronize()
+    assert int(counter.item()) == 2
+    Gref, Fref, _ = oracle_grad(pb, oracle_samples(pb, iteration=4))
+    assert abs(F1.item() - Fref) <= 1e-4 * max(1.0, abs(Fref))
+    assert F0.item() != F1.item()
+    assert max(rel_fro(pb.M.grad_views(p.grad), Gref)) <= 1e-5
+    p.grad = None
+
+
+def test_full_size_dense_200x200x200x200():
+    """The 200^4 FP32 workload (6.4 GB) at its full sample count: the fused
+    gradient and the autograd backward in FP32, and the BF16-storage gradient,
+    against the FP64 oracle on all 1e6 samples."""
+    announce("full size 200^4: data generation")
+    w = synth.dense_gaussian_200x200x200x200()
+    dev = torch.device("cuda:0")
+    Xd = torch.from_numpy(w.dense).to(dev)
+    X = gcp.dense_tensor(Xd)
+    # the oracle's uniform draws depend only on dims and the stream; x comes
+    # from the same FP32 array the device reads
+    smp = oracle.sample(w.sampler, w.dims, coo_idx=np.zeros((0, w.d), dtype=np.int64), coo_val=np.zeros(0),
+                        s=w.s, seed=w.seed, iteration=1)
+    smp.xval = w.dense[tuple(smp.idx.T)].astype(np.float64)
+    results = {}
+    for dtype in ("f32", "bf16"):
+        announce(f"full size 200^4: {dtype} storage")
+        M = gcp.Factors(w.dims, w.rank, {"f32": torch.float32, "bf16": torch.bfloat16}[dtype], dev, init=w.A_init)
+        cfg = gcp.sampling("uniform", s=w.s, seed=w.seed, iteration=1)
+        G = gcp.sampled_grad(w.loss, X, M, cfg)
+        sl = gcp.SampledLoss(w.loss, X, M, cfg)
+        p = sl.parameter()
+        sl(p).backward()
+        torch.cuda.synchronize()
+        Gref, _ = oracle.grad(w.loss, w.dims, host_rounded(w.A_init, dtype), smp, s=w.s)
+        assert max(rel_fro(G, Gref)) <= 1e-5
+        assert max(rel_fro(M.grad_views(p.grad), Gref)) <= 1e-5
+        # storage error: against the FP64 oracle on the unrounded (FP32) factors
+        G64, _ = oracle.grad(w.loss, w.dims, host_rounded(w.A_init, "f32"), smp, s=w.s)
+        results[dtype] = max(rel_fro(G, G64))
+        p.grad = None
+    print(f"[result] 200^4 gradient error vs FP64 on FP32 factors: FP32 storage {results['f32']:.2e}, "
+          f"BF16 storage {results['bf16']:.2e}", flush=True)
+    assert results["bf16"] < 5e-2

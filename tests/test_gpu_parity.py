@@ -19,7 +19,7 @@ from gpu_cases import (cfg_for, oracle_grad, oracle_samples, rel_fro, small_dens
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-12, "f32": 1e-5}
+TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 1e-5}  # bf16: the oracle sees the bf16-rounded factors
 
 
 def announce(msg):
@@ -141,8 +141,12 @@ CASES = [
     ("counts_semi_r64_d4", lambda: small_sparse("counts", dims=(30, 7, 11, 13), rank=64)),
     ("dense_f32_d5_r16", lambda: small_dense(dims=(7, 3, 4, 6, 5), rank=16, s=1111)),
     ("dense_f64_d2_r2", lambda: small_dense(dims=(40, 31), rank=2, s=777, dtype="f64")),
-    # mode 0 (3000 x 8 FP64 = 192 KB) exceeds the LDS budget: device-atomic fallback
-    ("counts_semi_long_mode", lambda: small_sparse("counts", dims=(3000, 7, 5), rank=8, p=20000, q=30000)),
+    # all modes (3012 x 8) fit in LDS only as FP32 partials (compare-and-swap adds)
+    ("counts_semi_fp32_lds", lambda: small_sparse("counts", dims=(3000, 7, 5), rank=8, p=20000, q=30000)),
+    ("dense_f32_r64_fp32_lds", lambda: small_dense(dims=(120, 110, 100), rank=64, s=5000)),
+    ("dense_bf16_r64_fp32_lds", lambda: small_dense(dims=(120, 110, 100), rank=64, s=5000, dtype="bf16")),
+    # mode 0 (6000 x 8) exceeds the LDS budget even in FP32: device-atomic fallback
+    ("counts_semi_long_mode", lambda: small_sparse("counts", dims=(6000, 7, 5), rank=8, p=20000, q=30000)),
 ]
 
 
