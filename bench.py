@@ -69,8 +69,8 @@ def algorithmic_bytes(w) -> float:
     return w.p * (per + 4 * d + bv) + w.q * (per + zero_data)
 
 
-KERNEL_SOURCES = ["paper_1906_01687_amd/csrc/grad.hip", "paper_1906_01687_amd/csrc/device.hpp",
-                  "paper_1906_01687_amd/csrc/common.hpp"]
+KERNEL_SOURCES = ["paper_1906_01687_amd/csrc/grad.hip", "paper_1906_01687_amd/csrc/grad_device.hpp",
+                  "paper_1906_01687_amd/csrc/device.hpp", "paper_1906_01687_amd/csrc/common.hpp"]
 
 
 def profiled_traffic(workload: str):

@@ -215,8 +215,10 @@ gcp_status gcp_loss_grad(gcp_loss loss, const gcp_tensor *X, const gcp_sampling 
  *   G[k]        out, dims[k] x rank row-major; F64 when M->dtype is GCP_F64,
  *               else F32.  Overwritten unless `accumulate` is non-zero.
  * Accumulation: each workgroup sums the modes whose rows fit in its LDS in
- * FP64 and publishes one partial (rounded to FP32); the partials are summed
- * in FP64 in a fixed order.  Longer modes are summed with FP64 device atomics.
+ * FP64 (or, for FP32/BF16 factors whose FP64 partial does not fit, in FP32)
+ * and publishes one partial (FP32; FP64 for FP64 factors); the partials are
+ * summed in FP64 in a fixed order.  Longer modes are summed with FP64 device
+ * atomics.
  * The workspace (gcp_mttkrp_workspace_bytes(X, M, S) bytes) holds both. */
 size_t gcp_mttkrp_workspace_bytes(const gcp_tensor *X, const gcp_factors *M, int64_t S);
 gcp_status gcp_mttkrp(const gcp_tensor *X, const gcp_factors *M, const uint32_t *idx,
