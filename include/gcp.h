@@ -280,6 +280,48 @@ gcp_status gcp_adam_step(int64_t P, gcp_dtype dtype, void *A, float *A_master,
                          double lower, gcp_eps_mode eps_mode, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * gcp_adam_fit -- GCP-Adam (Alg. 4) on one problem.  The loss is first
+ * estimated on one fixed sample set (EstObj: the weighted sum of f over the
+ * set, eqs. Fhat and Fhat-strat; `est` is drawn once).  Each epoch saves the
+ * parameters, moments and step count, takes `tau` fused sampled Adam steps
+ * (gcp_sampled_adam_step; the j-th step of the whole fit draws with
+ * iteration grad.iteration + j, so steps of an undone epoch are not redrawn)
+ * and estimates the loss again.  If the estimate rose, the epoch is undone
+ * (parameters, moments and step count restored, the estimate reverts), the
+ * learning rate is multiplied by nu and the count of bad epochs grows; the fit
+ * stops once that count exceeds kappa, or after max_epochs epochs.
+ *   A, A_master, B, C, state  as in gcp_sampled_adam_step (M->A[k] must be the
+ *               mode blocks of A); updated in place.
+ *   history     host, max_epochs + 1 doubles: [0] the first estimate, [e] the
+ *               estimate after epoch e (before any undo).
+ *   accepted    host, max_epochs + 1 bytes: 1 if epoch e was kept ([0] = 1).
+ *   epochs      host out: the number of epochs run.
+ *   alpha_out   host out (nullable): the final learning rate.
+ * The workspace holds the fused step's workspace, the estimation samples and
+ * the copies for undo (gcp_adam_fit_workspace_bytes).  The call synchronises
+ * `stream` once per epoch to read the estimate; it returns when the fit ends. */
+typedef struct gcp_fit_options {
+    gcp_sampling grad;           /* stochastic-gradient draws (iteration_counter ignored) */
+    gcp_sampling est;            /* the fixed estimation sample set */
+    double alpha;                /* learning rate (0.01 in the paper) */
+    double beta1, beta2, adam_eps;
+    double lower;                /* projection bound; -INFINITY for none */
+    double nu;                   /* learning-rate factor after a bad epoch (0.1) */
+    int32_t eps_mode;            /* gcp_eps_mode */
+    int32_t tau;                 /* steps per epoch (1000 in the paper), >= 1 */
+    int32_t kappa;               /* bad epochs tolerated (1), >= 0 */
+    int32_t max_epochs;          /* hard cap on epochs, >= 0 */
+} gcp_fit_options;
+
+size_t gcp_adam_fit_workspace_bytes(const gcp_tensor *X, const gcp_factors *M,
+                                    const gcp_fit_options *opt);
+gcp_status gcp_adam_fit(gcp_loss loss, const gcp_tensor *X, const gcp_factors *M,
+                        const gcp_fit_options *opt, double eps, void *A, float *A_master,
+                        void *B, void *C, int64_t *state, double *history, int8_t *accepted,
+                        int32_t *epochs, double *alpha_out, void *ws, size_t ws_bytes,
+                        hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Batches of independent problems: one persistent gradient launch and one
  * reduction + Adam launch advance every problem of the batch by one step of
  * Alg. 4's inner loop.  The persistent workgroups share the batch's samples

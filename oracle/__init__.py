@@ -7,7 +7,8 @@ import this package.  It loads ``liboracle.so``, built by gcc from
 Every function here is argument marshalling around the C oracle: the
 arithmetic (Philox draws, sampling, model entries, loss derivatives, the
 sparse MTTKRP and the Adam step) all lives in ``gcp_oracle.c`` and follows
-Kolda & Hong, Alg. 1-4 and eqs. Y, Gks, Fhat, Fhat-strat.
+Kolda & Hong, Alg. 1-4 and eqs. Y, Gks, Fhat, Fhat-strat.  ``adam_fit`` (the
+GCP-Adam epoch loop of Alg. 4) is plain Python control flow over those calls.
 """
 from __future__ import annotations
 
@@ -186,3 +187,78 @@ def adam(A, G, B, C, t: int, alpha=0.01, beta1=0.9, beta2=0.999, eps=1e-8,
     G64 = np.ascontiguousarray(G, dtype=np.float64)
     lib().orc_adam(A.size, _ptr(A), _ptr(G64), _ptr(B), _ptr(C), int(t), alpha, beta1, beta2,
                    eps, lower, eps_mode)
+
+
+def adam_fit(loss: int, dims, A0, *, dense=None, coo_idx=None, coo_val=None, grad_cfg: dict, est_cfg: dict,
+             alpha=0.01, beta1=0.9, beta2=0.999, eps=1e-8, lower=-np.inf, eps_mode: int = 0, nu=0.1,
+             tau=1000, kappa=1, max_epochs=100, loss_eps: float = LOSS_EPS):
+    """GCP-Adam (Alg. 4) in FP64.
+
+    ``grad_cfg`` and ``est_cfg`` are dicts with keys sampler, s, p, q, seed,
+    problem_id and (gradient draws only) iteration: the j-th Adam step of the
+    fit draws with iteration grad_cfg["iteration"] + j; the estimation set (EstObj, eqs. Fhat and
+    Fhat-strat) is drawn once and reused.  After each epoch of ``tau`` steps
+    the estimate is recomputed; if it rose, the epoch is undone (factors,
+    moments and step count), the learning rate is multiplied by ``nu`` and the
+    count of bad epochs grows; the loop ends when that count exceeds ``kappa``
+    or after ``max_epochs`` epochs.  Control flow only: every draw, gradient,
+    loss and Adam update is one of the calls above.
+
+    Returns (A, history, accepted, alpha): history[0] is the first estimate,
+    history[e] the estimate after epoch e; accepted[e] says if epoch e was kept.
+    """
+    d = len(dims)
+    data = dict(dense=dense) if dense is not None else dict(coo_idx=coo_idx, coo_val=coo_val)
+    nnz = 0 if coo_idx is None else int(np.asarray(coo_idx).shape[0])
+    sizes = [int(dims[k]) * int(A0[0].shape[1]) for k in range(d)]
+    A = np.concatenate([np.asarray(a, dtype=np.float64).reshape(-1) for a in A0])
+    B = np.zeros_like(A)
+    C = np.zeros_like(A)
+    r = A0[0].shape[1]
+
+    def mats(flat):
+        out, off = [], 0
+        for k in range(d):
+            out.append(flat[off:off + sizes[k]].reshape(dims[k], r))
+            off += sizes[k]
+        return out
+
+    def wkw(c):
+        return dict(nnz=nnz, s=c.get("s", 0), p=c.get("p", 0), q=c.get("q", 0))
+
+    est = est_cfg
+    est_smp = sample(est["sampler"], dims, s=est.get("s", 0), p=est.get("p", 0), q=est.get("q", 0),
+                     seed=est["seed"], problem_id=est.get("problem_id", 0), iteration=est.get("iteration", 0), **data)
+
+    def estimate():
+        return grad(loss, dims, mats(A), est_smp, eps=loss_eps, **wkw(est))[1]
+
+    F = estimate()
+    history, accepted = [F], [True]
+    bad, t, step, epoch = 0, 0, 0, 0
+    while bad <= kappa and epoch < max_epochs:
+        saved = (A.copy(), B.copy(), C.copy(), t)
+        F_old = F
+        for _ in range(tau):
+            g = grad_cfg
+            smp = sample(g["sampler"], dims, s=g.get("s", 0), p=g.get("p", 0), q=g.get("q", 0),
+                         seed=g["seed"], problem_id=g.get("problem_id", 0),
+                         iteration=g.get("iteration", 0) + step, **data)
+            step += 1
+            G, _ = grad(loss, dims, mats(A), smp, eps=loss_eps, **wkw(g))
+            t += 1
+            adam(A, np.concatenate([g.reshape(-1) for g in G]), B, C, t, alpha=alpha, beta1=beta1,
+                 beta2=beta2, eps=eps, lower=lower, eps_mode=eps_mode)
+        F = estimate()
+        epoch += 1
+        history.append(F)
+        if F > F_old:
+            A[:], B[:], C[:], t = saved[0], saved[1], saved[2], saved[3]
+            F = F_old
+            alpha *= nu
+            bad += 1
+            accepted.append(False)
+        else:
+            accepted.append(True)
+    return mats(A), history, accepted, alpha
+

@@ -66,12 +66,19 @@ class GcpBatchTuning(ctypes.Structure):
 BATCH_CONTIGUOUS, BATCH_LPT = 0, 1
 
 
+class GcpFitOptions(ctypes.Structure):
+    _fields_ = [("grad", GcpSampling), ("est", GcpSampling), ("alpha", ctypes.c_double),
+                ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("adam_eps", ctypes.c_double),
+                ("lower", ctypes.c_double), ("nu", ctypes.c_double), ("eps_mode", ctypes.c_int32),
+                ("tau", ctypes.c_int32), ("kappa", ctypes.c_int32), ("max_epochs", ctypes.c_int32)]
+
+
 EXPORTS = [
     "gcp_last_error", "gcp_abi_version", "gcp_nz_table_slots", "gcp_nz_table_bytes",
     "gcp_nz_index_build", "gcp_nz_bitmap_bytes", "gcp_nz_bitmap_build", "gcp_sample_workspace_bytes", "gcp_sample", "gcp_loss_grad",
     "gcp_mttkrp_workspace_bytes", "gcp_mttkrp", "gcp_sampled_grad_workspace_bytes",
     "gcp_sampled_grad", "gcp_sampled_adam_step", "gcp_adam_step", "gcp_timing_start",
-    "gcp_timing_stop", "gcp_batched_create", "gcp_batched_workspace_bytes", "gcp_batched_prepare", "gcp_batched_plan",
+    "gcp_timing_stop", "gcp_batched_create", "gcp_batched_workspace_bytes", "gcp_batched_prepare", "gcp_batched_plan", "gcp_adam_fit_workspace_bytes", "gcp_adam_fit",
     "gcp_batched_grad", "gcp_batched_adam_step", "gcp_batched_destroy",
 ]
 
@@ -115,6 +122,9 @@ def lib() -> ctypes.CDLL:
         "gcp_batched_grad": (st, [P, P, P]),
         "gcp_batched_adam_step": (st, [P, P, P, dbl, dbl, dbl, dbl, ctypes.c_int, P]),
         "gcp_batched_plan": (st, [P, P, P, P, P, P]),
+        "gcp_adam_fit_workspace_bytes": (sz, [P, P, ctypes.POINTER(GcpFitOptions)]),
+        "gcp_adam_fit": (st, [ctypes.c_int, P, P, ctypes.POINTER(GcpFitOptions), dbl, P, P, P, P, P, P, P, P,
+                              P, P, sz, P]),
         "gcp_batched_destroy": (None, [P]),
         "gcp_timing_start": (st, [i64]),
         "gcp_timing_stop": (st, [ctypes.POINTER(dbl), ctypes.POINTER(i64)]),

@@ -341,6 +341,44 @@ class Adam:
                                   int(self.eps_mode), _stream(stream)))
 
 
+@dataclasses.dataclass
+class FitResult:
+    history: List[float]      # [0] first estimate, [e] estimate after epoch e
+    accepted: List[bool]      # epoch e kept (False: undone)
+    epochs: int
+    alpha: float              # final learning rate
+    adam: "Adam"
+
+
+def adam_fit(loss, X: DataTensor, M: Factors, grad: GcpSampling, est: GcpSampling, *, lr: float = 0.01,
+             beta1: float = 0.9, beta2: float = 0.999, adam_eps: float = 1e-8, lower: float = -math.inf,
+             nu: float = 0.1, tau: int = 1000, kappa: int = 1, max_epochs: int = 100,
+             eps_mode: int = _lib.EPS_INSIDE_SQRT, eps: float = LOSS_EPS, adam: Optional["Adam"] = None,
+             stream=None) -> FitResult:
+    """gcp_adam_fit: GCP-Adam (Alg. 4) on M in place, with the loss estimated on
+    the fixed sample set ``est`` once per epoch."""
+    L = lib()
+    adam = adam or Adam(M, lr=lr, beta1=beta1, beta2=beta2, eps=adam_eps, lower=lower, eps_mode=eps_mode)
+    o = _lib.GcpFitOptions()
+    o.grad, o.est = grad, est
+    o.alpha, o.beta1, o.beta2, o.adam_eps = float(lr), float(beta1), float(beta2), float(adam_eps)
+    o.lower, o.nu, o.eps_mode = float(lower), float(nu), int(eps_mode)
+    o.tau, o.kappa, o.max_epochs = int(tau), int(kappa), int(max_epochs)
+    t, m = X.struct(), M.struct()
+    nbytes = int(L.gcp_adam_fit_workspace_bytes(ctypes.byref(t), ctypes.byref(m), ctypes.byref(o)))
+    if nbytes == 0:
+        raise _lib.GcpError(1, L.gcp_last_error().decode())
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=X.values.device)
+    hist = (ctypes.c_double * (max_epochs + 1))()
+    acc = (ctypes.c_int8 * (max_epochs + 1))()
+    ep, alpha = ctypes.c_int32(), ctypes.c_double()
+    check(L.gcp_adam_fit(_loss_code(loss), ctypes.byref(t), ctypes.byref(m), ctypes.byref(o), float(eps),
+                         _ptr(M.flat), _ptr(M.master), _ptr(adam.B), _ptr(adam.C), _ptr(adam.state), hist, acc,
+                         ctypes.byref(ep), ctypes.byref(alpha), _ptr(ws), nbytes, _stream(stream)))
+    n = ep.value
+    return FitResult([hist[i] for i in range(n + 1)], [bool(acc[i]) for i in range(n + 1)], n, alpha.value, adam)
+
+
 # ---------------------------------------------------------------------------
 # batches of independent problems (gcp_batched_*)
 # ---------------------------------------------------------------------------

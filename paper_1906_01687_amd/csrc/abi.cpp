@@ -6,6 +6,7 @@
 #include <math.h>
 #include <stdio.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -546,6 +547,170 @@ gcp_status gcp_batched_plan(const gcp_batch* batch, int64_t* n_blocks, int64_t* 
 }
 
 void gcp_batched_destroy(gcp_batch* batch) { batch_destroy(batch); }
+
+// ---------------------------------------------------------------------------
+// GCP-Adam driver (Alg. 4): host control flow over the entry points above.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct FitLayout {
+    void* step_ws;
+    size_t step_bytes;
+    uint32_t* idx;
+    void* xval;
+    uint8_t* stratum;
+    void* ytilde;
+    void* sample_ws;
+    size_t sample_bytes;
+    double* loss_sum;
+    void* A_save;
+    float* master_save;
+    void* B_save;
+    void* C_save;
+    int64_t* state_save;
+    int64_t S_est, P;
+    size_t esz, msz;
+};
+
+size_t fit_layout(const gcp_tensor* X, const gcp_factors* M, const gcp_fit_options* opt, void* base,
+                  FitLayout* L) {
+    FitLayout f{};
+    int64_t P = 0;
+    for (int k = 0; k < X->d; ++k) P += X->dims[k] * M->rank;
+    f.P = P;
+    f.esz = M->dtype == GCP_F64 ? 8 : (M->dtype == GCP_F32 ? 4 : 2);
+    f.msz = M->dtype == GCP_F64 ? 8 : 4;
+    const size_t vsz = X->vdtype == GCP_F64 ? 8 : 4;
+    f.S_est = opt->est.sampler == GCP_SAMPLER_UNIFORM ? opt->est.s : opt->est.p + opt->est.q;
+    gcp_sampling grad = opt->grad;
+    grad.iteration_counter = nullptr;
+    gcp_sampling est = opt->est;
+    est.iteration_counter = nullptr;
+    f.step_bytes = gcp_sampled_grad_workspace_bytes(X, M, &grad);
+    f.sample_bytes = gcp_sample_workspace_bytes(X, &est);
+    Carver c;
+    f.step_ws = c.take<char>(base, std::max<size_t>(1, f.step_bytes));
+    f.idx = c.take<uint32_t>(base, (size_t)std::max<int64_t>(1, f.S_est) * (size_t)X->d);
+    f.xval = c.take<char>(base, (size_t)std::max<int64_t>(1, f.S_est) * vsz);
+    f.stratum = c.take<uint8_t>(base, (size_t)std::max<int64_t>(1, f.S_est));
+    f.ytilde = c.take<char>(base, (size_t)std::max<int64_t>(1, f.S_est) * f.msz);
+    f.sample_ws = c.take<char>(base, std::max<size_t>(1, f.sample_bytes));
+    f.loss_sum = c.take<double>(base, 1);
+    f.A_save = c.take<char>(base, (size_t)std::max<int64_t>(1, P) * f.esz);
+    f.master_save = c.take<float>(base, M->dtype == GCP_BF16 ? (size_t)std::max<int64_t>(1, P) : 1);
+    f.B_save = c.take<char>(base, (size_t)std::max<int64_t>(1, P) * f.msz);
+    f.C_save = c.take<char>(base, (size_t)std::max<int64_t>(1, P) * f.msz);
+    f.state_save = c.take<int64_t>(base, 2);
+    if (L) *L = f;
+    return c.bytes();
+}
+
+gcp_status check_fit(const gcp_tensor* X, const gcp_factors* M, const gcp_fit_options* opt) {
+    if (!opt) return set_error(GCP_ERR_INVALID_ARG, "opt is NULL");
+    if (opt->tau < 1) return set_error(GCP_ERR_INVALID_ARG, "opt->tau must be >= 1");
+    if (opt->kappa < 0) return set_error(GCP_ERR_INVALID_ARG, "opt->kappa must be >= 0");
+    if (opt->max_epochs < 0) return set_error(GCP_ERR_INVALID_ARG, "opt->max_epochs must be >= 0");
+    if (!(opt->nu > 0.0 && opt->nu <= 1.0)) return set_error(GCP_ERR_INVALID_ARG, "opt->nu must be in (0, 1]");
+    if (gcp_status st = check_tensor(X)) return st;
+    if (gcp_status st = check_sampling(X, &opt->grad)) return st;
+    if (gcp_status st = check_sampling(X, &opt->est)) return st;
+    if (gcp_status st = check_factors(X, M)) return st;
+    return GCP_OK;
+}
+
+gcp_status copy_async(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return GCP_OK;
+    if (hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return set_error(GCP_ERR_HIP, "device copy failed");
+    return GCP_OK;
+}
+
+}  // namespace
+
+size_t gcp_adam_fit_workspace_bytes(const gcp_tensor* X, const gcp_factors* M, const gcp_fit_options* opt) {
+    clear_error();
+    if (check_fit(X, M, opt) != GCP_OK) return 0;
+    return fit_layout(X, M, opt, nullptr, nullptr);
+}
+
+gcp_status gcp_adam_fit(gcp_loss loss, const gcp_tensor* X, const gcp_factors* M, const gcp_fit_options* opt,
+                        double eps, void* A, float* A_master, void* B, void* C, int64_t* state, double* history,
+                        int8_t* accepted, int32_t* epochs, double* alpha_out, void* ws, size_t ws_bytes,
+                        hipStream_t stream) {
+    clear_error();
+    if (gcp_status st = check_loss(loss)) return st;
+    if (gcp_status st = check_fit(X, M, opt)) return st;
+    if (!history || !accepted || !epochs) return set_error(GCP_ERR_INVALID_ARG, "history, accepted and epochs are required");
+    FitLayout f{};
+    const size_t need = fit_layout(X, M, opt, ws, &f);
+    if (!ws || ws_bytes < need)
+        return set_error(GCP_ERR_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
+    gcp_sampling grad = opt->grad;
+    grad.iteration_counter = nullptr;
+    gcp_sampling est = opt->est;
+    est.iteration_counter = nullptr;
+    // the fixed estimation set
+    if (gcp_status st = gcp_sample(X, &est, f.idx, f.xval, f.stratum, f.sample_ws, f.sample_bytes, stream)) return st;
+    auto estimate = [&](double* F) -> gcp_status {
+        if (gcp_status st = launch_fill_zero(f.loss_sum, 1, stream)) return st;
+        if (gcp_status st = gcp_loss_grad(loss, X, &est, M, f.idx, f.xval, f.stratum, f.S_est, eps, f.ytilde,
+                                          f.loss_sum, stream))
+            return st;
+        if (hipMemcpyAsync(F, f.loss_sum, sizeof(double), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess)
+            return set_error(GCP_ERR_HIP, "reading the loss estimate failed");
+        return GCP_OK;
+    };
+    const size_t pa = (size_t)f.P * f.esz, pm = (size_t)f.P * f.msz;
+    auto save = [&](bool restore) -> gcp_status {
+        // restore = false: parameters -> copies; true: copies -> parameters
+        auto cp = [&](void* live, void* copy, size_t bytes) {
+            return restore ? copy_async(live, copy, bytes, stream) : copy_async(copy, live, bytes, stream);
+        };
+        if (gcp_status st = cp(A, f.A_save, pa)) return st;
+        if (M->dtype == GCP_BF16)
+            if (gcp_status st = cp(A_master, f.master_save, (size_t)f.P * 4)) return st;
+        if (gcp_status st = cp(B, f.B_save, pm)) return st;
+        if (gcp_status st = cp(C, f.C_save, pm)) return st;
+        return cp(state, f.state_save, 2 * sizeof(int64_t));
+    };
+    double F = 0.0;
+    if (gcp_status st = estimate(&F)) return st;
+    history[0] = F;
+    accepted[0] = 1;
+    double alpha = opt->alpha;
+    int32_t bad = 0, epoch = 0;
+    uint64_t step = 0;
+    while (bad <= opt->kappa && epoch < opt->max_epochs) {
+        if (gcp_status st = save(false)) return st;
+        const double F_old = F;
+        for (int32_t j = 0; j < opt->tau; ++j) {
+            grad.iteration = opt->grad.iteration + step++;
+            if (gcp_status st = gcp_sampled_adam_step(loss, X, M, &grad, eps, A, A_master, B, C, state, alpha,
+                                                      opt->beta1, opt->beta2, opt->adam_eps, opt->lower,
+                                                      (gcp_eps_mode)opt->eps_mode, nullptr, nullptr, f.step_ws,
+                                                      f.step_bytes, stream))
+                return st;
+        }
+        if (gcp_status st = estimate(&F)) return st;
+        ++epoch;
+        history[epoch] = F;
+        if (F > F_old) {
+            // undo the epoch: parameters, moments and step count; smaller steps
+            if (gcp_status st = save(true)) return st;
+            F = F_old;
+            alpha *= opt->nu;
+            ++bad;
+            accepted[epoch] = 0;
+        } else {
+            accepted[epoch] = 1;
+        }
+    }
+    if (hipStreamSynchronize(stream) != hipSuccess) return set_error(GCP_ERR_HIP, "hipStreamSynchronize failed");
+    *epochs = epoch;
+    if (alpha_out) *alpha_out = alpha;
+    return GCP_OK;
+}
 
 gcp_status gcp_timing_start(int64_t max_launches) {
     clear_error();

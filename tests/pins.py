@@ -447,6 +447,74 @@ def pin_finite_differences(loss, h=None):
     return worst <= tol, f"worst rel {worst:.3e}"
 
 
+def cp_score(A_true, A_est):
+    """Cosine similarity score of App. E: mean over components of the product
+    over modes of column cosines, under the best column matching."""
+    from scipy.optimize import linear_sum_assignment
+    r = A_true[0].shape[1]
+    S = np.ones((r, r))
+    for a, b in zip(A_true, A_est):
+        an = a / np.linalg.norm(a, axis=0)
+        bn = b / np.linalg.norm(b, axis=0)
+        S *= an.T @ bn
+    ri, ci = linear_sum_assignment(-S)
+    return float(S[ri, ci].mean())
+
+
+def pin_cp_score():
+    """The score is 1 for the same model up to column order, column scaling and
+    sign flips in pairs of modes, and near 0 for unrelated factors."""
+    rng = np.random.default_rng(9)
+    A = [rng.standard_normal((n, 4)) for n in (9, 8, 7)]
+    perm = np.array([2, 0, 3, 1])
+    scale = [np.array([2.0, 0.5, 3.0, 1.0]), np.array([1.0, 4.0, 0.25, 1.0]), np.array([0.5, 0.5, 1.0, 1.0])]
+    B = [a[:, perm] * s_ for a, s_ in zip(A, scale)]
+    B[0][:, 1] *= -1
+    B[2][:, 1] *= -1
+    if abs(cp_score(A, B) - 1.0) > 1e-12:
+        return False, "equivalent model"
+    C = [rng.standard_normal(a.shape) for a in A]
+    sc = cp_score(A, C)
+    return sc < 0.3, f"unrelated score {sc:.3f}"
+
+
+def pin_adam_fit_recovers():
+    """GCP-Adam (Alg. 4) with the oracle's gradients recovers the factors of a
+    noisy rank-3 Gaussian tensor from a random start (score >= 0.9, App. E),
+    and the accepted estimates never rise."""
+    dims, r = (20, 15, 10), 3
+    rng = np.random.default_rng(41)
+    A_true = [rng.standard_normal((n, r)) for n in dims]
+    X = full_model(A_true) + 0.1 * rng.standard_normal(dims)
+    A0 = [rng.standard_normal((n, r)) for n in dims]
+    A, hist, acc, _ = oracle.adam_fit(oracle.GAUSSIAN, dims, A0, dense=X,
+                                      grad_cfg=dict(sampler=oracle.UNIFORM, s=300, seed=5),
+                                      est_cfg=dict(sampler=oracle.UNIFORM, s=3000, seed=6),
+                                      alpha=0.01, tau=500, kappa=3, max_epochs=40)
+    kept = [h for h, a in zip(hist, acc) if a]
+    mono = all(b <= a for a, b in zip(kept, kept[1:]))
+    sc = cp_score(A_true, A)
+    return sc >= 0.9 and mono, f"score {sc:.4f}, kept estimates non-increasing {mono}"
+
+
+def pin_adam_fit_undo():
+    """An epoch that raises the estimate is undone exactly: with a step size
+    that overshoots, every epoch is undone, so the fit returns the start
+    unchanged after kappa + 1 epochs with the rate scaled by nu^(kappa+1)."""
+    dims, r = (6, 5, 4), 2
+    rng = np.random.default_rng(43)
+    A_true = [rng.standard_normal((n, r)) for n in dims]
+    X = full_model(A_true)
+    A0 = [rng.standard_normal((n, r)) for n in dims]
+    A, hist, acc, alpha = oracle.adam_fit(oracle.GAUSSIAN, dims, A0, dense=X,
+                                          grad_cfg=dict(sampler=oracle.UNIFORM, s=40, seed=7),
+                                          est_cfg=dict(sampler=oracle.UNIFORM, s=500, seed=8),
+                                          alpha=50.0, nu=0.5, tau=5, kappa=2, max_epochs=10)
+    same = all(np.array_equal(a, b) for a, b in zip(A, A0))
+    ok = same and acc == [True, False, False, False] and len(hist) == 4 and abs(alpha - 50.0 * 0.125) < 1e-12
+    return ok, f"unchanged {same}, accepted {acc}, alpha {alpha}"
+
+
 ALL_PINS = {
     "philox_numpy": pin_philox_numpy,
     "randi_exact": pin_randi_exact,
@@ -466,4 +534,7 @@ ALL_PINS = {
     "fd_gaussian": lambda: pin_finite_differences(oracle.GAUSSIAN),
     "fd_bernoulli_stratified": lambda: pin_finite_differences(oracle.BERNOULLI_ODDS),
     "fd_poisson_semi": lambda: pin_finite_differences(oracle.POISSON),
+    "cp_score": pin_cp_score,
+    "adam_fit_recovers": pin_adam_fit_recovers,
+    "adam_fit_undo": pin_adam_fit_undo,
 }

@@ -40,6 +40,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(m.GcpTensor) == 128
     assert ctypes.sizeof(m.GcpFactors) == 80
     assert ctypes.sizeof(m.GcpSampling) == 72
+    assert ctypes.sizeof(m.GcpFitOptions) == 208
 
 
 def test_host_queries():
@@ -255,3 +256,30 @@ def test_batch_plan_covers_every_item_once(schedule, unit_items):
     h = ctypes.c_void_p()
     assert L.gcp_batched_create(arr, 1, ctypes.byref(bad), ctypes.byref(h)) == 1
     assert b"schedule" in L.gcp_last_error()
+
+
+def test_fit_options_are_checked():
+    """gcp_adam_fit validates its options on the host (no launch)."""
+    m = _lib()
+    L = m.lib()
+    t = _dense_struct(m, (30, 40, 50))
+    M = m.GcpFactors()
+    M.dtype, M.rank = m.F32, 4
+    for k in range(3):
+        M.A[k] = 0x10000
+    o = m.GcpFitOptions()
+    o.grad.sampler, o.grad.s = m.UNIFORM, 100
+    o.est.sampler, o.est.s = m.UNIFORM, 1000
+    o.alpha, o.beta1, o.beta2, o.adam_eps, o.nu = 0.01, 0.9, 0.999, 1e-8, 0.1
+    o.tau, o.kappa, o.max_epochs = 10, 1, 5
+    assert L.gcp_adam_fit_workspace_bytes(ctypes.byref(t), ctypes.byref(M), ctypes.byref(o)) > 0
+    o.tau = 0
+    assert L.gcp_adam_fit_workspace_bytes(ctypes.byref(t), ctypes.byref(M), ctypes.byref(o)) == 0
+    assert b"tau" in L.gcp_last_error()
+    o.tau, o.nu = 10, 0.0
+    hist = (ctypes.c_double * 6)()
+    acc = (ctypes.c_int8 * 6)()
+    ep = ctypes.c_int32()
+    st = L.gcp_adam_fit(0, ctypes.byref(t), ctypes.byref(M), ctypes.byref(o), 1e-10, 0x10000, None, 0x20000,
+                        0x30000, 0x40000, hist, acc, ctypes.byref(ep), None, 0x50000, 1 << 30, None)
+    assert st == 1 and b"nu" in L.gcp_last_error()
