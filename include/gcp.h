@@ -60,15 +60,21 @@ typedef enum gcp_status {
 
 typedef enum gcp_dtype { GCP_F32 = 0, GCP_F64 = 1, GCP_BF16 = 2 } gcp_dtype;
 
-/* Losses f(x, m) and g = df/dm (paper, Sec. 1 and 4.2).  eps is added where
- * the paper writes log m or x/m:
+/* Losses f(x, m) and g = df/dm (paper, Sec. 1, 4.2 and 5.3).  eps is added
+ * where the paper divides by m or takes log m or a power of m (u = m + eps):
  *   GAUSSIAN        f = (x - m)^2,                  g = 2 (m - x)
- *   BERNOULLI_ODDS  f = log(m + 1) - x log(m + eps), g = 1/(m + 1) - x/(m + eps)
- *   POISSON         f = m - x log(m + eps),          g = 1 - x/(m + eps)        */
+ *   BERNOULLI_ODDS  f = log(m + 1) - x log u,        g = 1/(m + 1) - x/u
+ *   POISSON         f = m - x log u,                 g = 1 - x/u
+ *   GAMMA           f = x/u + log u,                 g = 1/u - x/u^2
+ *   BETA_HALF       f = 2 u^(1/2) + 2 x u^(-1/2),    g = u^(-1/2) - x u^(-3/2)
+ * (GAMMA: shape-1 Gamma data, Sec. 1 and the Sec. 5.2 test problems;
+ * BETA_HALF: beta-divergence with beta = 1/2 up to terms free of m, Sec. 5.3.) */
 typedef enum gcp_loss {
     GCP_LOSS_GAUSSIAN = 0,
     GCP_LOSS_BERNOULLI_ODDS = 1,
-    GCP_LOSS_POISSON = 2
+    GCP_LOSS_POISSON = 2,
+    GCP_LOSS_GAMMA = 3,
+    GCP_LOSS_BETA_HALF = 4
 } gcp_loss;
 
 /* Samplers: UNIFORM (Sec. 4.1, Alg. 1; s draws with replacement, weight

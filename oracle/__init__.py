@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gcp_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-GAUSSIAN, BERNOULLI_ODDS, POISSON = 0, 1, 2
+GAUSSIAN, BERNOULLI_ODDS, POISSON, GAMMA, BETA_HALF = 0, 1, 2, 3, 4
 UNIFORM, STRATIFIED, SEMI_STRATIFIED = 0, 1, 2
 S_UNIFORM, S_NZ, S_ZERO, S_NZ_CORR, S_SEMI_ZERO = 0, 1, 2, 3, 4
 LOSS_EPS = 1e-10

@@ -38,7 +38,7 @@ static int g_mutation = 0;
 void orc_set_mutation(int m) { g_mutation = m; }
 int orc_get_mutation(void) { return g_mutation; }
 
-enum { ORC_GAUSSIAN = 0, ORC_BERNOULLI_ODDS = 1, ORC_POISSON = 2 };
+enum { ORC_GAUSSIAN = 0, ORC_BERNOULLI_ODDS = 1, ORC_POISSON = 2, ORC_GAMMA = 3, ORC_BETA_HALF = 4 };
 enum { ORC_UNIFORM = 0, ORC_STRATIFIED = 1, ORC_SEMI = 2 };
 /* sample stratum codes (one per sample) */
 enum { ORC_S_UNIFORM = 0, ORC_S_NZ = 1, ORC_S_ZERO = 2, ORC_S_NZ_CORR = 3, ORC_S_SEMI_ZERO = 4 };
@@ -95,6 +95,10 @@ double orc_loss_f(int loss, double x, double m, double eps)
     case ORC_GAUSSIAN:       return (x - m) * (x - m);
     case ORC_BERNOULLI_ODDS: return log(m + 1.0) - x * log(m + eps);
     case ORC_POISSON:        return m - x * log(m + eps);
+    /* Gamma with shape 1 (Sec. 1): x/m + log m */
+    case ORC_GAMMA:          return x / (m + eps) + log(m + eps);
+    /* beta-divergence with beta = 1/2 (Sec. 5.3): 2 m^(1/2) + 2 x m^(-1/2) */
+    case ORC_BETA_HALF:      return 2.0 * sqrt(m + eps) + 2.0 * x / sqrt(m + eps);
     }
     return NAN;
 }
@@ -107,6 +111,8 @@ double orc_loss_g(int loss, double x, double m, double eps)
         return 2.0 * (m - x);
     case ORC_BERNOULLI_ODDS: return 1.0 / (m + 1.0) - x / (m + eps);
     case ORC_POISSON:        return 1.0 - x / (m + eps);
+    case ORC_GAMMA:          return 1.0 / (m + eps) - x / ((m + eps) * (m + eps));
+    case ORC_BETA_HALF:      return 1.0 / sqrt(m + eps) - x / ((m + eps) * sqrt(m + eps));
     }
     return NAN;
 }

@@ -18,7 +18,8 @@ import torch
 from . import _lib
 from ._lib import (BF16, COO, DENSE, F32, F64, GcpFactors, GcpSampling, GcpTensor, check, lib)
 
-LOSSES = {"gaussian": _lib.GAUSSIAN, "bernoulli_odds": _lib.BERNOULLI_ODDS, "poisson": _lib.POISSON}
+LOSSES = {"gaussian": _lib.GAUSSIAN, "bernoulli_odds": _lib.BERNOULLI_ODDS, "poisson": _lib.POISSON,
+          "gamma": _lib.GAMMA, "beta_half": _lib.BETA_HALF}
 SAMPLERS = {"uniform": _lib.UNIFORM, "stratified": _lib.STRATIFIED, "semi_stratified": _lib.SEMI_STRATIFIED}
 LOSS_EPS = 1e-10
 

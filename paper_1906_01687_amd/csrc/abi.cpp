@@ -179,7 +179,8 @@ static gcp_status check_factors(const gcp_tensor* X, const gcp_factors* M) {
 }
 
 static gcp_status check_loss(gcp_loss loss) {
-    if (loss != GCP_LOSS_GAUSSIAN && loss != GCP_LOSS_BERNOULLI_ODDS && loss != GCP_LOSS_POISSON)
+    if (loss != GCP_LOSS_GAUSSIAN && loss != GCP_LOSS_BERNOULLI_ODDS && loss != GCP_LOSS_POISSON &&
+        loss != GCP_LOSS_GAMMA && loss != GCP_LOSS_BETA_HALF)
         return set_error(GCP_ERR_INVALID_ARG, "loss is not a gcp_loss");
     return GCP_OK;
 }

@@ -166,6 +166,8 @@ template <typename T>
 __device__ __forceinline__ T loss_g(int loss, T x, T m, T eps) {
     if (loss == GCP_LOSS_GAUSSIAN) return T(2) * (m - x);
     if (loss == GCP_LOSS_BERNOULLI_ODDS) return T(1) / (m + T(1)) - x / (m + eps);
+    if (loss == GCP_LOSS_GAMMA) return T(1) / (m + eps) - x / ((m + eps) * (m + eps));
+    if (loss == GCP_LOSS_BETA_HALF) return T(1) / sqrt(m + eps) - x / ((m + eps) * sqrt(m + eps));
     return T(1) - x / (m + eps);
 }
 
@@ -173,6 +175,8 @@ template <typename T>
 __device__ __forceinline__ T loss_f(int loss, T x, T m, T eps) {
     if (loss == GCP_LOSS_GAUSSIAN) return (x - m) * (x - m);
     if (loss == GCP_LOSS_BERNOULLI_ODDS) return log(m + T(1)) - x * log(m + eps);
+    if (loss == GCP_LOSS_GAMMA) return x / (m + eps) + log(m + eps);
+    if (loss == GCP_LOSS_BETA_HALF) return T(2) * sqrt(m + eps) + T(2) * x / sqrt(m + eps);
     return m - x * log(m + eps);
 }
 

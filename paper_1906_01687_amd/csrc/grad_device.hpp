@@ -220,8 +220,11 @@ __device__ __forceinline__ T group_sum(T m, int lps) {
 // x / y: IEEE division in FP64; reciprocal (1 ulp) and product in FP32.
 __device__ __forceinline__ double quot(double x, double y) { return x / y; }
 __device__ __forceinline__ float quot(float x, float y) { return x * __builtin_amdgcn_rcpf(y); }
+// 1 / sqrt(y): FP64 from the correctly rounded root; FP32 hardware (1 ulp).
+__device__ __forceinline__ double rroot(double y) { return 1.0 / sqrt(y); }
+__device__ __forceinline__ float rroot(float y) { return __builtin_amdgcn_rsqf(y); }
 
-// w * g(x, m) for the loss's derivative g (Sec. 1 and 4.2); for a corrected
+// w * g(x, m) for the loss's derivative g (Sec. 1, 4.2 and 5.3); for a corrected
 // nonzero of semi-stratified sampling (Sec. 4.3, Alg. 3), w * (g(x, m) -
 // g(0, m)), which keeps only the part of g that depends on x.
 template <typename T>
@@ -231,8 +234,20 @@ __device__ __forceinline__ T weighted_g(int loss, T x, T m, T w, T eps) {
     if (loss == GCP_LOSS_GAUSSIAN) {
         g = corr ? T(-2) * x : T(2) * (m - x);
     } else {
-        const T t = quot(x, m + eps);
-        const T base = loss == GCP_LOSS_BERNOULLI_ODDS ? quot(T(1), m + T(1)) : T(1);
+        // g = base(m) - t(x, m): the x-free part and the part linear in x
+        T base, t;
+        if (loss == GCP_LOSS_GAMMA) {
+            const T u = quot(T(1), m + eps);
+            base = u;
+            t = x * u * u;
+        } else if (loss == GCP_LOSS_BETA_HALF) {
+            const T u = rroot(m + eps);
+            base = u;
+            t = x * u * u * u;
+        } else {
+            t = quot(x, m + eps);
+            base = loss == GCP_LOSS_BERNOULLI_ODDS ? quot(T(1), m + T(1)) : T(1);
+        }
         g = corr ? -t : base - t;
     }
     return (corr ? -w : w) * g;

@@ -25,6 +25,9 @@ Workloads (dims, rank, loss, sampler; data recipe):
   generated in slabs).  X = [[A1..A4]] with N(0,1) factor entries plus
   0.1*N(0,1) noise; Gaussian loss; uniform sampling, s = 1e6; factors stored
   in FP32 or BF16 (``_bf16``); evaluated at an independent N(0,1) start.
+* ``dense_gamma_200x150x100x50`` -- the Gamma test problem of App. C at the
+  shape and rank of the paper's Gamma study (Sec. 5.2): U(0,1) factors, rank
+  5, entries Gamma(shape 1, mean m); FP32 data (600 MB); uniform sampling.
 * ``batch_of_cubes`` -- 64 dense cubes, sides round(exp(U(ln 20, ln 300))),
   ranks uniform over {4, 8, 16, 32}, losses b mod 3 with the data of the
   recipes above, s = ceil(2% of the entries) uniform samples each.
@@ -40,7 +43,7 @@ from typing import List, Optional
 
 import numpy as np
 
-GAUSSIAN, BERNOULLI_ODDS, POISSON = 0, 1, 2
+GAUSSIAN, BERNOULLI_ODDS, POISSON, GAMMA, BETA_HALF = 0, 1, 2, 3, 4
 UNIFORM, STRATIFIED, SEMI_STRATIFIED = 0, 1, 2
 
 _CACHE = os.environ.get("GCP_DATA_CACHE",
@@ -318,6 +321,28 @@ def dense_gaussian_200x200x200x200(dtype="f32", s=1_000_000) -> Workload:
                     seed=4003, lr=1e-3)
 
 
+def dense_gamma(dims, rank, seed):
+    """Gamma test problem of the paper's App. C: factor entries U(0,1); every
+    entry x ~ Gamma(shape 1, mean m) (exponential with mean m).  Returns
+    (X float64, A_true)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    A = [rng.random((n, rank)) for n in dims]
+    M = _full(A)
+    X = rng.exponential(1.0, size=M.shape) * M
+    return X, A
+
+
+def dense_gamma_200x150x100x50(s=2000) -> Workload:
+    """The shape and rank of the paper's Gamma study (Sec. 5.2): 200x150x100x50,
+    rank 5, FP32 data (600 MB), uniform sampling, nonnegative factors."""
+    dims, r = (200, 150, 100, 50), 5
+    X, A_true = dense_gamma(dims, r, seed=6001)
+    rng = np.random.Generator(np.random.PCG64(6002))
+    A0 = [rng.random((n, r)) for n in dims]
+    return Workload("dense_gamma_200x150x100x50", dims, r, GAMMA, UNIFORM, "f32", s=s, dense=X.astype(np.float32),
+                    A_true=A_true, A_init=A0, seed=6003, lower=0.0)
+
+
 def sparse_binary_1000x800x600() -> Workload:
     return sparse_binary_workload()
 
@@ -332,6 +357,7 @@ WORKLOADS = {
     "sparse_count_6000x24x77x32": sparse_count_6000x24x77x32,
     "dense_gaussian_200x200x200x200": dense_gaussian_200x200x200x200,
     "dense_gaussian_200x200x200x200_bf16": lambda: dense_gaussian_200x200x200x200("bf16"),
+    "dense_gamma_200x150x100x50": dense_gamma_200x150x100x50,
 }
 
 
@@ -343,7 +369,8 @@ def dense_problem(n_dims, rank, loss, seed, density=None):
     """A dense problem with the recipe of its loss: Gaussian N(0,1) factors plus
     0.1 noise; Poisson counts from Gamma(0.5,1) factors scaled to `density`
     nonzeros; Bernoulli(odds) from U(0,1) factors scaled to mean probability
-    `density`.  Returns (X float64 dense, start factors, projection bound)."""
+    `density`; Gamma and beta-divergence: shape-1 Gamma data with mean m from
+    U(0,1) factors.  Returns (X float64 dense, start factors, projection bound)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     dims = tuple(n_dims)
     d = len(dims)
@@ -352,6 +379,12 @@ def dense_problem(n_dims, rank, loss, seed, density=None):
         X = _full(A) + 0.1 * rng.standard_normal(dims)
         A0 = [rng.standard_normal((n, rank)) for n in dims]
         return X, A0, -np.inf
+    if loss in (GAMMA, BETA_HALF):
+        # positive data: shape-1 Gamma with mean m from U(0,1) factors (App. C)
+        A = [rng.random((n, rank)) for n in dims]
+        X = rng.exponential(1.0, size=dims) * _full(A)
+        A0 = [rng.random((n, rank)) for n in dims]
+        return X, A0, 0.0
     if loss == POISSON:
         A = [rng.gamma(0.5, 1.0, size=(n, rank)) for n in dims]
         M = _full(A)

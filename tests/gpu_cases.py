@@ -100,7 +100,10 @@ def rel_fro(gpu_list, ref_list) -> List[float]:
 def small_dense(dims=(13, 17, 11), rank=5, s=3001, dtype="f32", loss=synth.GAUSSIAN, seed=501):
     X, _ = synth.dense_gaussian(dims, rank, seed=seed)
     A0 = synth.gaussian_start(dims, rank, seed=seed + 1)
-    if loss != synth.GAUSSIAN:
+    if loss in (synth.GAMMA, synth.BETA_HALF):
+        X = np.abs(X) + 0.05
+        A0 = [np.abs(a) + 0.05 for a in A0]
+    elif loss != synth.GAUSSIAN:
         X = np.round(np.abs(X)) if loss == synth.POISSON else (np.abs(X) > 1.0).astype(float)
         A0 = [np.abs(a) + 0.05 for a in A0]
     return synth.Workload(f"dense{dims}", tuple(dims), rank, loss, synth.UNIFORM, dtype, s=s, dense=X,
@@ -108,7 +111,8 @@ def small_dense(dims=(13, 17, 11), rank=5, s=3001, dtype="f32", loss=synth.GAUSS
 
 
 def small_sparse(kind="binary", dims=(61, 47, 33), rank=7, p=2111, q=3333, sampler=None, dtype="f32",
-                 seed=601):
+                 seed=601, loss=None):
+    loss_override = loss
     if kind == "binary":
         coo, val, _, scale = synth.sparse_binary(dims, rank, 0.03, seed=seed, subsample=50000)
         A0 = synth.nonneg_start(dims, rank, seed + 1, "uniform", scale)
@@ -120,5 +124,5 @@ def small_sparse(kind="binary", dims=(61, 47, 33), rank=7, p=2111, q=3333, sampl
         A0 = synth.nonneg_start(dims, rank, seed + 1, "gamma", scale)
         loss = synth.POISSON
         sampler = synth.SEMI_STRATIFIED if sampler is None else sampler
-    return synth.Workload(f"{kind}{dims}", tuple(dims), rank, loss, sampler, dtype, p=p, q=q, coo_idx=coo,
-                          coo_val=val, A_init=A0, seed=seed + 2, lower=0.0)
+    return synth.Workload(f"{kind}{dims}", tuple(dims), rank, loss if loss_override is None else loss_override,
+                          sampler, dtype, p=p, q=q, coo_idx=coo, coo_val=val, A_init=A0, seed=seed + 2, lower=0.0)

@@ -297,8 +297,10 @@ def pin_poisson_closed_form():
 
 def pin_loss_likelihoods():
     """Losses from their likelihoods: Bernoulli with odds m has P(x=1) = m/(1+m);
-    Poisson f = -log pmf(x; m) - log x!; Gaussian f = (x - m)^2.  Derivatives by
-    central differences of f."""
+    Poisson f = -log pmf(x; m) - log x!; Gaussian f = (x - m)^2; shape-1 Gamma
+    f = -log density of the exponential with mean m; beta = 1/2 f = the
+    beta-divergence d(x|m) plus a term free of m.  Derivatives by central
+    differences of f."""
     for m in [0.01, 0.3, 1.0, 4.5]:
         if abs(oracle.loss_f(oracle.BERNOULLI_ODDS, 1.0, m, 0.0) + math.log(m / (1 + m))) > 1e-12:
             return False, "bernoulli x=1"
@@ -311,7 +313,19 @@ def pin_loss_likelihoods():
         for x in [-1.5, 0.0, 2.0]:
             if abs(oracle.loss_f(oracle.GAUSSIAN, x, m, 0.0) - (x - m) ** 2) > 1e-14:
                 return False, "gaussian"
-    for loss in (oracle.GAUSSIAN, oracle.BERNOULLI_ODDS, oracle.POISSON):
+    for m in [0.05, 0.7, 2.5]:
+        for x in [0.01, 0.4, 3.0]:
+            # shape-1 Gamma (exponential with mean m): f = -log density
+            ref = -scipy.stats.expon.logpdf(x, scale=m)
+            if abs(oracle.loss_f(oracle.GAMMA, x, m, 0.0) - ref) > 1e-12 * max(1, abs(ref)):
+                return False, f"gamma x={x} m={m}"
+            # beta-divergence, beta = 1/2: d(x|m) = (x^b + (b-1) m^b - b x m^(b-1)) / (b (b-1));
+            # f differs from it by 4 sqrt(x), which does not depend on m
+            b = 0.5
+            dbeta = (x ** b + (b - 1) * m ** b - b * x * m ** (b - 1)) / (b * (b - 1))
+            if abs(oracle.loss_f(oracle.BETA_HALF, x, m, 0.0) - dbeta - 4 * math.sqrt(x)) > 1e-12 * max(1, abs(dbeta)):
+                return False, f"beta x={x} m={m}"
+    for loss in (oracle.GAUSSIAN, oracle.BERNOULLI_ODDS, oracle.POISSON, oracle.GAMMA, oracle.BETA_HALF):
         for x in [0.0, 1.0, 2.0]:
             for m in [0.2, 1.3, 3.0]:
                 h = 1e-5
@@ -423,6 +437,20 @@ def pin_finite_differences(loss, h=None):
         smp = oracle.sample(oracle.UNIFORM, dims, dense=X, s=30, seed=4)
         kw = dict(s=30)
         h = h or 1e-3
+    elif loss == oracle.GAMMA:
+        X, A = tiny_dense((4, 3, 5), r=3)
+        X = np.abs(X) + 0.1
+        A = [np.abs(a) + 0.2 for a in A]
+        dims = X.shape
+        smp = oracle.sample(oracle.UNIFORM, dims, dense=X, s=30, seed=4)
+        kw = dict(s=30)
+        h = h or 1e-6
+    elif loss == oracle.BETA_HALF:
+        X, coo, val, A = tiny_sparse("counts")
+        dims = X.shape
+        smp = oracle.sample(oracle.SEMI_STRATIFIED, dims, coo_idx=coo, coo_val=val, p=9, q=11, seed=4)
+        kw = dict(nnz=coo.shape[0], p=9, q=11)
+        h = h or 1e-6
     else:
         X, coo, val, A = tiny_sparse("binary" if loss == oracle.BERNOULLI_ODDS else "counts")
         dims = X.shape
@@ -529,11 +557,15 @@ ALL_PINS = {
     "unbiased_stratified_bernoulli": lambda: pin_unbiased(oracle.STRATIFIED, oracle.BERNOULLI_ODDS),
     "unbiased_semi_poisson": lambda: pin_unbiased(oracle.SEMI_STRATIFIED, oracle.POISSON),
     "unbiased_semi_bernoulli": lambda: pin_unbiased(oracle.SEMI_STRATIFIED, oracle.BERNOULLI_ODDS),
+    "unbiased_semi_beta_half": lambda: pin_unbiased(oracle.SEMI_STRATIFIED, oracle.BETA_HALF),
+    "unbiased_stratified_gamma": lambda: pin_unbiased(oracle.STRATIFIED, oracle.GAMMA),
     "semi_zero_half_poisson": pin_semi_zero_half_poisson,
     "adam_closed_forms": pin_adam_closed_forms,
     "fd_gaussian": lambda: pin_finite_differences(oracle.GAUSSIAN),
     "fd_bernoulli_stratified": lambda: pin_finite_differences(oracle.BERNOULLI_ODDS),
     "fd_poisson_semi": lambda: pin_finite_differences(oracle.POISSON),
+    "fd_gamma_uniform": lambda: pin_finite_differences(oracle.GAMMA),
+    "fd_beta_half_semi": lambda: pin_finite_differences(oracle.BETA_HALF),
     "cp_score": pin_cp_score,
     "adam_fit_recovers": pin_adam_fit_recovers,
     "adam_fit_undo": pin_adam_fit_undo,

@@ -42,13 +42,14 @@ def make_problem(w, pid, dtype=None, keep_grad=True):
 def mixed_workloads(dtype="f32"):
     """Dense cubes of several sides, ranks and losses plus sparse semi-stratified problems."""
     out = []
-    specs = [(9, 1, 0), (17, 4, 1), (23, 7, 2), (31, 16, 0), (12, 33, 1), (40, 8, 2), (26, 5, 0)]
+    losses = [synth.GAUSSIAN, synth.POISSON, synth.BERNOULLI_ODDS, synth.GAMMA, synth.BETA_HALF]
+    specs = [(9, 1, 0), (17, 4, 1), (23, 7, 2), (31, 16, 0), (12, 33, 1), (40, 8, 2), (26, 5, 0), (15, 6, 3),
+             (21, 3, 4)]
     for b, (n, r, loss) in enumerate(specs):
-        X, A0, lower = synth.dense_problem((n, n, n), r, [synth.GAUSSIAN, synth.POISSON, synth.BERNOULLI_ODDS][loss],
-                                           seed=900 + b, density=0.05 if loss else None)
-        out.append(synth.Workload(f"cube{b}", (n, n, n), r, [synth.GAUSSIAN, synth.POISSON, synth.BERNOULLI_ODDS][loss],
-                                  synth.UNIFORM, dtype, s=max(37, int(0.03 * n ** 3)), dense=X, A_init=A0, seed=77,
-                                  lower=lower))
+        X, A0, lower = synth.dense_problem((n, n, n), r, losses[loss], seed=900 + b,
+                                           density=0.05 if loss in (1, 2) else None)
+        out.append(synth.Workload(f"cube{b}", (n, n, n), r, losses[loss], synth.UNIFORM, dtype,
+                                  s=max(37, int(0.03 * n ** 3)), dense=X, A_init=A0, seed=77, lower=lower))
     out.append(small_sparse("counts", dims=(41, 23, 17), rank=10, p=1500, q=2100, dtype=dtype))
     out.append(small_sparse("binary", dims=(33, 29, 18), rank=6, p=900, q=1300, dtype=dtype,
                             sampler=synth.SEMI_STRATIFIED))

@@ -106,3 +106,26 @@ def test_fit_recovers_low_rank_factors(dtype):
     print(f"[result] recovery {dtype}: score {score:.4f} after {res.epochs} epochs, final estimate "
           f"{res.history[-1]:.4g}", flush=True)
     assert score >= 0.9
+
+
+def test_fit_recovers_gamma_factors():
+    """GCP-Adam with the Gamma loss on the App. C test problem (U(0,1) factors,
+    shape-1 Gamma data), nonnegative projection, FP32."""
+    announce("gcp_adam_fit recovery, Gamma loss")
+    import synth
+    dims, r = (30, 25, 20, 15), 3
+    X, A_true = synth.dense_gamma(dims, r, seed=71)
+    rng = np.random.default_rng(72)
+    A0 = [rng.random((n, r)) for n in dims]
+    dev = torch.device("cuda:0")
+    Xt = gcp.dense_tensor(torch.as_tensor(X).to(torch.float32).to(dev))
+    M = gcp.Factors(dims, r, torch.float32, dev, init=A0)
+    res = gcp.adam_fit("gamma", Xt, M, gcp.sampling("uniform", s=500, seed=5),
+                       gcp.sampling("uniform", s=20000, seed=6), lr=0.01, lower=0.0, tau=500, kappa=3,
+                       max_epochs=40)
+    torch.cuda.synchronize()
+    A = [a.detach().to(torch.float64).cpu().numpy() for a in M.A]
+    score = cp_score(A_true, A)
+    print(f"[result] Gamma recovery: score {score:.4f} after {res.epochs} epochs", flush=True)
+    assert score >= 0.9
+    assert min(float(a.min()) for a in A) >= 0.0

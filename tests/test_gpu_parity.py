@@ -141,6 +141,10 @@ CASES = [
     ("counts_semi_r64_d4", lambda: small_sparse("counts", dims=(30, 7, 11, 13), rank=64)),
     ("dense_f32_d5_r16", lambda: small_dense(dims=(7, 3, 4, 6, 5), rank=16, s=1111)),
     ("dense_f64_d2_r2", lambda: small_dense(dims=(40, 31), rank=2, s=777, dtype="f64")),
+    ("dense_f32_gamma_r6", lambda: small_dense(rank=6, loss=synth.GAMMA)),
+    ("dense_f64_beta_r4", lambda: small_dense(rank=4, loss=synth.BETA_HALF, dtype="f64")),
+    ("counts_semi_beta_r10", lambda: small_sparse("counts", rank=10, loss=synth.BETA_HALF)),
+    ("counts_strat_gamma_r5", lambda: small_sparse("counts", rank=5, sampler=synth.STRATIFIED, loss=synth.GAMMA)),
     # all modes (3012 x 8) fit in LDS only as FP32 partials (compare-and-swap adds)
     ("counts_semi_fp32_lds", lambda: small_sparse("counts", dims=(3000, 7, 5), rank=8, p=20000, q=30000)),
     ("dense_f32_r64_fp32_lds", lambda: small_dense(dims=(120, 110, 100), rank=64, s=5000)),
