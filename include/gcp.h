@@ -123,6 +123,14 @@ typedef struct gcp_tensor {
                                     linear key L.  When given, the rejection test of
                                     STRATIFIED reads it instead of the hash table
                                     (one load instead of a probe sequence). */
+    const void *weights;         /* optional entry weights w_i of the weighted
+                                    objective sum_i w_i f(x_i, m_i) (eq. wgcp,
+                                    Sec. 4.4), type vdtype: dense, one per entry;
+                                    COO, one per stored entry.  NULL: all 1. */
+    double w_zero;               /* with weights on a COO tensor: the weight of
+                                    every entry it does not store (zeros; 0 for
+                                    missing data).  Ignored without weights or
+                                    for dense tensors. */
 } gcp_tensor;
 
 /* The factor matrices A_1..A_d of the CP model (eq. Mdef). */
@@ -204,7 +212,9 @@ gcp_status gcp_sample(const gcp_tensor *X, const gcp_sampling *cfg,
 /* ---------------------------------------------------------------------------
  * gcp_loss_grad -- model entries and weighted derivatives at given samples
  * (Alg. 1-3: m_i = sum_j prod_k A_k(i_k, j), then ytilde_i += w g(x_i, m_i)).
- * Weights come from the stratum codes, X's dims and nnz, and cfg's s, p, q.
+ * Weights come from the stratum codes, X's dims and nnz, and cfg's s, p, q,
+ * times the entry weights of X when it has them (a weighted COO tensor then
+ * needs nz_table, through which a sample's stored weight is found).
  *   ytilde[S]   out; F64 when M->dtype is GCP_F64, else F32 (computed in F32)
  *   loss_sum    nullable device double; the call ADDS the weighted loss
  *               estimate sum_i w f(x_i, m_i) (eqs. Fhat, Fhat-strat; for the

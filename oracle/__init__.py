@@ -61,6 +61,11 @@ def lib():
         L.orc_grad.argtypes = [ctypes.c_int, ctypes.c_int, P, i64, P, i64, P, P, P,
                                i64, i64, i64, i64, dbl, P, P]
         L.orc_grad.restype = dbl
+        L.orc_grad_weighted.argtypes = [ctypes.c_int, ctypes.c_int, P, i64, P, i64, P, P, P, P, dbl,
+                                        i64, i64, i64, i64, dbl, P, P]
+        L.orc_grad_weighted.restype = dbl
+        L.orc_entry_weights.argtypes = [ctypes.c_int, P, P, i64, P, P, dbl, i64, P, P, P]
+        L.orc_entry_weights.restype = ctypes.c_int
         L.orc_full_grad.argtypes = [ctypes.c_int, ctypes.c_int, P, i64, P, P, dbl, P]
         L.orc_full_grad.restype = dbl
         L.orc_adam.argtypes = [i64, P, P, P, P, i64, dbl, dbl, dbl, dbl, dbl, ctypes.c_int]
@@ -144,9 +149,37 @@ def _factor_ptrs(A):
     return A64, arr
 
 
+def entry_weights(dims, smp: Samples, *, dense_w=None, coo_idx=None, coo_w=None, w_zero: float = 1.0):
+    """The weight w_i of eq. wgcp at every sample: a stored entry's own weight,
+    w_zero for entries a COO tensor does not store (and for zero samples)."""
+    d = len(dims)
+    dims_a = np.ascontiguousarray(dims, dtype=np.int64)
+    S = len(smp)
+    idx = np.ascontiguousarray(smp.idx, dtype=np.int64).reshape(-1)
+    st = np.ascontiguousarray(smp.stratum, dtype=np.int32)
+    out = np.zeros(max(S, 1), dtype=np.float64)
+    keep = []
+    if dense_w is not None:
+        wd = np.ascontiguousarray(dense_w, dtype=np.float64).reshape(-1)
+        keep.append(wd)
+        rc = lib().orc_entry_weights(d, _ptr(dims_a), _ptr(wd), 0, None, None, float(w_zero), S, _ptr(idx),
+                                     _ptr(st), _ptr(out))
+    else:
+        ci = np.ascontiguousarray(coo_idx, dtype=np.int64).reshape(-1, d)
+        cw = np.ascontiguousarray(coo_w, dtype=np.float64).reshape(-1)
+        keep += [ci, cw]
+        rc = lib().orc_entry_weights(d, _ptr(dims_a), None, ci.shape[0], _ptr(ci), _ptr(cw), float(w_zero), S,
+                                     _ptr(idx), _ptr(st), _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle entry_weights: bad arguments")
+    return out[:S]
+
+
 def grad(loss: int, dims, A, smp: Samples, *, nnz: int = 0, s: int = 0, p: int = 0, q: int = 0,
-         eps: float = LOSS_EPS, want_ytilde: bool = False):
-    """Sampled gradient G_k (list of n_k x r float64) and the loss estimate."""
+         eps: float = LOSS_EPS, want_ytilde: bool = False, wgt=None, w_zero: float = 1.0):
+    """Sampled gradient G_k (list of n_k x r float64) and the loss estimate;
+    with ``wgt`` (entry weights per sample, see entry_weights) that of the
+    weighted objective of eq. wgcp."""
     d = len(dims)
     r = A[0].shape[1]
     dims_a = np.ascontiguousarray(dims, dtype=np.int64)
@@ -158,8 +191,13 @@ def grad(loss: int, dims, A, smp: Samples, *, nnz: int = 0, s: int = 0, p: int =
     xv = np.ascontiguousarray(smp.xval, dtype=np.float64)
     st = np.ascontiguousarray(smp.stratum, dtype=np.int32)
     yt = np.zeros(max(S, 1), dtype=np.float64)
-    F = lib().orc_grad(loss, d, _ptr(dims_a), r, Ap, S, _ptr(idx), _ptr(xv), _ptr(st),
-                       nnz, s, p, q, eps, _ptr(yt), Gp)
+    if wgt is None:
+        F = lib().orc_grad(loss, d, _ptr(dims_a), r, Ap, S, _ptr(idx), _ptr(xv), _ptr(st),
+                           nnz, s, p, q, eps, _ptr(yt), Gp)
+    else:
+        wg = np.ascontiguousarray(wgt, dtype=np.float64)
+        F = lib().orc_grad_weighted(loss, d, _ptr(dims_a), r, Ap, S, _ptr(idx), _ptr(xv), _ptr(st), _ptr(wg),
+                                    float(w_zero), nnz, s, p, q, eps, _ptr(yt), Gp)
     if want_ytilde:
         return G, F, yt[:S]
     return G, F

@@ -249,6 +249,34 @@ done:
     return ret;
 }
 
+/* Entry weights of the weighted objective sum_i w_i f(x_i, m_i) (eq. wgcp,
+ * Sec. 4.4) at each sample: a stored entry's own weight (dense: wdense[L];
+ * COO: coo_w of the stored entry), w_zero for an entry a COO tensor does not
+ * store.  Zero samples (stratified) are such entries; the "zeros" of
+ * semi-stratified sampling stand for every entry at x = 0 in the correction
+ * scheme, so they take w_zero as well.  Returns 0, or -1 on bad arguments. */
+int orc_entry_weights(int d, const int64_t *dims, const double *wdense, int64_t nnz, const int64_t *coo_idx,
+                      const double *coo_w, double w_zero, int64_t S, const int64_t *idx, const int32_t *stratum,
+                      double *wout)
+{
+    if (d < 1 || d > 8) return -1;
+    keypos *kp = NULL;
+    if (!wdense) kp = sorted_nonzeros(d, dims, nnz, coo_idx);
+    for (int64_t c = 0; c < S; ++c) {
+        const int64_t *i = idx + c * d;
+        if (stratum[c] == ORC_S_ZERO || stratum[c] == ORC_S_SEMI_ZERO) {
+            wout[c] = w_zero;
+        } else if (wdense) {
+            wout[c] = wdense[linear_key(d, dims, i)];
+        } else {
+            int64_t e = find_nonzero(kp, nnz, linear_key(d, dims, i));
+            wout[c] = (e >= 0) ? coo_w[e] : w_zero;
+        }
+    }
+    free(kp);
+    return 0;
+}
+
 /* Per-stratum weights (Sec. 4.1-4.3).  ytilde = w * (g(x,m) - corr * g(0,m)). */
 static double stratum_weight(int st, double omega, double eta, int64_t s, int64_t p, int64_t q)
 {
@@ -285,10 +313,28 @@ static double model_entry(int d, int64_t r, const double *const *A, const int64_
 /* correction argument applied to f -- parity unpinned as a paper formula,   */
 /* pinned here only by its expectation).                                     */
 /* ------------------------------------------------------------------------ */
+double orc_grad_weighted(int loss, int d, const int64_t *dims, int64_t r, const double *const *A,
+                         int64_t S, const int64_t *idx, const double *xval, const int32_t *stratum,
+                         const double *wgt, double w_zero, int64_t nnz, int64_t s, int64_t p, int64_t q,
+                         double eps, double *ytilde_out, double *const *G);
+
 double orc_grad(int loss, int d, const int64_t *dims, int64_t r, const double *const *A,
                 int64_t S, const int64_t *idx, const double *xval, const int32_t *stratum,
                 int64_t nnz, int64_t s, int64_t p, int64_t q, double eps,
                 double *ytilde_out, double *const *G)
+{
+    return orc_grad_weighted(loss, d, dims, r, A, S, idx, xval, stratum, NULL, 1.0, nnz, s, p, q, eps,
+                             ytilde_out, G);
+}
+
+/* The same with entry weights (eq. wgcp: ytilde_i = s_i w_i g(x_i, m_i) for
+ * the sampling weight s_i; a corrected nonzero gives s_i (w_i g(x,m) - w_zero
+ * g(0,m)), so that with the semi-stratified "zeros" (weight w_zero) the
+ * estimate stays unbiased for sum_i w_i f(x_i, m_i)).  wgt NULL: all 1. */
+double orc_grad_weighted(int loss, int d, const int64_t *dims, int64_t r, const double *const *A,
+                         int64_t S, const int64_t *idx, const double *xval, const int32_t *stratum,
+                         const double *wgt, double w_zero, int64_t nnz, int64_t s, int64_t p, int64_t q,
+                         double eps, double *ytilde_out, double *const *G)
 {
     double omega = 1.0;
     for (int k = 0; k < d; ++k) omega *= (double)dims[k];
@@ -301,14 +347,16 @@ double orc_grad(int loss, int d, const int64_t *dims, int64_t r, const double *c
         int st = stratum[c];
         double m = model_entry(d, r, A, i);
         double w = stratum_weight(st, omega, eta, s, p, q);
+        double we = wgt ? wgt[c] : 1.0;
+        double wz = wgt ? ((g_mutation == 7) ? we : w_zero) : 1.0;   /* 7 planted: own weight in the correction */
         double y, f;
         if (st == ORC_S_NZ_CORR) {
-            y = (g_mutation == 4) ? w * orc_loss_g(loss, x, m, eps)      /* planted: no correction */
-                                  : w * (orc_loss_g(loss, x, m, eps) - orc_loss_g(loss, 0.0, m, eps));
-            f = w * (orc_loss_f(loss, x, m, eps) - orc_loss_f(loss, 0.0, m, eps));
+            y = (g_mutation == 4) ? w * we * orc_loss_g(loss, x, m, eps)      /* planted: no correction */
+                                  : w * (we * orc_loss_g(loss, x, m, eps) - wz * orc_loss_g(loss, 0.0, m, eps));
+            f = w * (we * orc_loss_f(loss, x, m, eps) - wz * orc_loss_f(loss, 0.0, m, eps));
         } else {
-            y = w * orc_loss_g(loss, x, m, eps);
-            f = w * orc_loss_f(loss, x, m, eps);
+            y = w * we * orc_loss_g(loss, x, m, eps);
+            f = w * we * orc_loss_f(loss, x, m, eps);
         }
         if (ytilde_out) ytilde_out[c] = y;
         F += f;

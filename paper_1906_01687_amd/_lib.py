@@ -36,7 +36,8 @@ class GcpTensor(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("format", ctypes.c_int32), ("vdtype", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("dims", ctypes.c_int64 * GCP_MAX_D),
                 ("values", ctypes.c_void_p), ("coo_idx", ctypes.c_void_p), ("nnz", ctypes.c_int64),
-                ("nz_table", ctypes.c_void_p), ("nz_slots", ctypes.c_int64), ("nz_bitmap", ctypes.c_void_p)]
+                ("nz_table", ctypes.c_void_p), ("nz_slots", ctypes.c_int64), ("nz_bitmap", ctypes.c_void_p),
+                ("weights", ctypes.c_void_p), ("w_zero", ctypes.c_double)]
 
 
 class GcpFactors(ctypes.Structure):

@@ -57,6 +57,8 @@ class DataTensor:
     nz_table: Optional[torch.Tensor] = None     # uint8 bytes of the nonzero hash
     nz_slots: int = 0
     nz_bitmap: Optional[torch.Tensor] = None    # int32 words of the membership bitmap
+    weights: Optional[torch.Tensor] = None      # entry weights (eq. wgcp), same dtype and layout as values
+    w_zero: float = 1.0                         # COO with weights: weight of the entries not stored
 
     @property
     def d(self) -> int:
@@ -87,26 +89,42 @@ class DataTensor:
         t.nz_table = _ptr(self.nz_table)
         t.nz_slots = int(self.nz_slots)
         t.nz_bitmap = _ptr(self.nz_bitmap)
+        t.weights = _ptr(self.weights)
+        t.w_zero = float(self.w_zero)
         return t
 
 
-def dense_tensor(X: torch.Tensor) -> DataTensor:
+def _check_weights(weights: Optional[torch.Tensor], values: torch.Tensor) -> Optional[torch.Tensor]:
+    if weights is None:
+        return None
+    if weights.dtype != values.dtype or weights.shape != values.shape or weights.device != values.device:
+        raise ValueError("weights must match the values in dtype, shape and device")
+    return weights.contiguous()
+
+
+def dense_tensor(X: torch.Tensor, weights: Optional[torch.Tensor] = None) -> DataTensor:
+    """Dense row-major X; ``weights`` (same shape) gives the entry weights of
+    the weighted objective (eq. wgcp), e.g. 0 for missing entries."""
     if X.dtype not in (torch.float32, torch.float64) or not X.is_contiguous():
         raise ValueError("dense X must be a contiguous float32/float64 tensor")
-    return DataTensor(tuple(X.shape), X)
+    return DataTensor(tuple(X.shape), X, weights=_check_weights(weights, X))
 
 
 BITMAP_LIMIT_BYTES = 1 << 30
 
 
 def coo_tensor(dims: Sequence[int], coo_idx: torch.Tensor, values: torch.Tensor,
-               build_index: bool = True, bitmap: Optional[bool] = None, stream=None) -> DataTensor:
+               build_index: bool = True, bitmap: Optional[bool] = None, stream=None,
+               weights: Optional[torch.Tensor] = None, w_zero: float = 1.0) -> DataTensor:
     """COO tensor; builds the nonzero hash (gcp_nz_index_build) unless told not
     to, and the membership bitmap (gcp_nz_bitmap_build) when ``bitmap`` is True,
-    or when it is None and the bitmap takes at most BITMAP_LIMIT_BYTES."""
+    or when it is None and the bitmap takes at most BITMAP_LIMIT_BYTES.
+    ``weights`` (one per stored entry) and ``w_zero`` (every other entry) give
+    the weighted objective of eq. wgcp."""
     if coo_idx.dtype != torch.int32 or coo_idx.dim() != 2 or coo_idx.shape[1] != len(dims):
         raise ValueError("coo_idx must be an [nnz, d] int32 tensor")
-    X = DataTensor(tuple(int(n) for n in dims), values.contiguous(), coo_idx.contiguous())
+    X = DataTensor(tuple(int(n) for n in dims), values.contiguous(), coo_idx.contiguous(),
+                   weights=_check_weights(weights, values), w_zero=float(w_zero))
     if build_index:
         L = lib()
         slots = int(L.gcp_nz_table_slots(X.nnz))

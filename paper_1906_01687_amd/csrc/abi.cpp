@@ -4,6 +4,8 @@
 #include <hip/hip_runtime_api.h>
 
 #include <math.h>
+
+#include <cmath>
 #include <stdio.h>
 
 #include <algorithm>
@@ -53,6 +55,22 @@ void stratum_weights(const gcp_tensor* X, const gcp_sampling* cfg, double w[5]) 
     w[GCP_STRATUM_ZERO] = cfg->q > 0 ? (omega - eta) / (double)cfg->q : 0.0;
     w[GCP_STRATUM_NZ_CORR] = w[GCP_STRATUM_NZ];
     w[GCP_STRATUM_SEMI_ZERO] = cfg->q > 0 ? omega / (double)cfg->q : 0.0;
+    // weighted objective (eq. wgcp): entries a COO tensor does not store weigh
+    // w_zero, so the zero strata carry it; stored entries get theirs per sample
+    const double wz = zero_weight(X);
+    w[GCP_STRATUM_ZERO] *= wz;
+    w[GCP_STRATUM_SEMI_ZERO] *= wz;
+}
+
+double zero_weight(const gcp_tensor* X) {
+    return (X->weights && X->format == GCP_COO) ? X->w_zero : 1.0;
+}
+
+double corr_zero_weight(const gcp_tensor* X, const gcp_sampling* cfg) {
+    // the g(0, m) part of a corrected nonzero: (eta / p) * w_zero
+    double w[5];
+    stratum_weights(X, cfg, w);
+    return w[GCP_STRATUM_NZ_CORR] * zero_weight(X);
 }
 
 int64_t rejection_batch(const gcp_tensor* X, const gcp_sampling* cfg) {
@@ -105,6 +123,8 @@ static gcp_status check_tensor(const gcp_tensor* X) {
         return set_error(GCP_ERR_INVALID_ARG, "X->format must be GCP_DENSE or GCP_COO");
     if (X->vdtype != GCP_F32 && X->vdtype != GCP_F64)
         return set_error(GCP_ERR_INVALID_ARG, "X->vdtype must be GCP_F32 or GCP_F64");
+    if (X->weights && !std::isfinite(X->w_zero))
+        return set_error(GCP_ERR_INVALID_ARG, "X->w_zero must be finite");
     for (int k = 0; k < X->d; ++k)
         if (X->dims[k] < 1 || X->dims[k] > (int64_t)0xFFFFFFFFll)
             return set_error(GCP_ERR_INVALID_ARG, "X->dims[" + std::to_string(k) + "] must be in [1, 2^32 - 1]");
@@ -421,6 +441,11 @@ gcp_status gcp_loss_grad(gcp_loss loss, const gcp_tensor* X, const gcp_sampling*
     if (S == 0) return GCP_OK;
     if (!idx || !xval || !stratum || !ytilde)
         return set_error(GCP_ERR_INVALID_ARG, "idx, xval, stratum and ytilde must be non-NULL");
+    if (X->weights && X->format == GCP_COO && X->nnz > 0) {
+        // the stored samples carry indices only: a nonzero's weight is found
+        // through the index table
+        if (gcp_status st = check_table(X)) return st;
+    }
     return launch_loss_grad(loss, X, cfg, M, idx, xval, stratum, S, eps, ytilde, loss_sum, stream);
 }
 

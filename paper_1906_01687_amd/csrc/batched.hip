@@ -119,10 +119,10 @@ __global__ __launch_bounds__(1024) void batched_grad_kernel(BatchGradArgs ba) {
             Sample<D, T> smp = no_sample<D, T>();
             if (c < a.n_direct) {
                 uint32_t i[D];
-                T x;
+                T x, ew;
                 int code;
-                produce<D, VT, T>(a, iter, c, i, x, code);
-                smp = make_sample<D, T>(a, i, x, code);
+                produce<D, VT, T>(a, iter, c, i, x, code, ew);
+                smp = make_sample<D, T>(a, i, x, code, ew);
             }
             return smp;
         };
@@ -341,6 +341,9 @@ gcp_status batch_create(const gcp_problem* problems, int32_t count, const gcp_ba
             B->lds_fp32[b] = 0;
         }
         stratum_weights(&pr.X, &pr.cfg, a.w);
+        a.kz = corr_zero_weight(&pr.X, &pr.cfg);
+        a.weights = pr.X.weights;
+        a.w_zero = zero_weight(&pr.X);
         a.eps = pr.eps;
         B->args[b] = a;
         B->flat_off[b] = flat;

@@ -144,6 +144,8 @@ gcp_status launch_bump_counter(uint64_t* counter, hipStream_t s);
 
 // Stratum weights for X and cfg (omega/s, eta/p, zeta/q, eta/p, omega/q).
 void stratum_weights(const gcp_tensor* X, const gcp_sampling* cfg, double w[5]);
+double zero_weight(const gcp_tensor* X);
+double corr_zero_weight(const gcp_tensor* X, const gcp_sampling* cfg);
 
 gcp_status launch_loss_grad(gcp_loss loss, const gcp_tensor* X, const gcp_sampling* cfg,
                             const gcp_factors* M, const uint32_t* idx, const void* xval,

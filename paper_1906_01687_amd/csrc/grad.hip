@@ -107,10 +107,10 @@ __device__ __forceinline__ Sample<D, typename Compute<FT>::type> item_sample(con
                 smp = make_sample<D, T>(a, i, static_cast<const T*>(a.ytilde)[c], GCP_STRATUM_UNIFORM);
                 smp.w = T(1);
             } else {
-                T x;
+                T x, ew;
                 int code;
-                produce<D, VT, T>(a, iter, c, i, x, code);
-                smp = make_sample<D, T>(a, i, x, code);
+                produce<D, VT, T>(a, iter, c, i, x, code, ew);
+                smp = make_sample<D, T>(a, i, x, code, ew);
             }
         }
     } else if constexpr (!LIST) {
@@ -247,6 +247,12 @@ struct LossArgs {
     double eps;
     void* ytilde;
     double* loss_sum;
+    // weighted objective (eq. wgcp); see GradArgs
+    const void* weights;
+    double w_zero;
+    double kz;
+    int format;
+    NzTable tab;
 };
 
 template <int NB, int D, typename FT>
@@ -285,13 +291,8 @@ __device__ __forceinline__ void loss_passes(const LossArgs& a, const __amdgpu_bu
             const T m = group_sum(prod[u], lps);
             const int64_t cs = item * kWave + src[u];
             if (j == 0 && p0 + u < lps && cs < a.S) {
-                static_cast<T*>(a.ytilde)[cs] = weighted_g(a.loss, xx[u], m, ww[u], eps);
-                if (a.loss_sum) {
-                    const bool corr = ww[u] < T(0);
-                    T f = loss_f<T>(a.loss, xx[u], m, eps);
-                    if (corr) f -= loss_f<T>(a.loss, T(0), m, eps);
-                    fsum += (corr ? -ww[u] : ww[u]) * f;
-                }
+                static_cast<T*>(a.ytilde)[cs] = weighted_g(a.loss, xx[u], m, ww[u], eps, (T)a.kz);
+                if (a.loss_sum) fsum += weighted_f(a.loss, xx[u], m, ww[u], eps, (T)a.kz);
             }
         }
     }
@@ -319,11 +320,29 @@ __global__ __launch_bounds__(256) void loss_grad_kernel(LossArgs a) {
         const int64_t c = item * kWave + lane;
         Sample<D, T> smp = no_sample<D, T>();
         if (c < a.S) {
+            uint32_t i[D];
 #pragma unroll
-            for (int k = 0; k < D; ++k) smp.q[k] = a.idx[c * D + k] * (uint32_t)a.r;
+            for (int k = 0; k < D; ++k) i[k] = a.idx[c * D + k];
+#pragma unroll
+            for (int k = 0; k < D; ++k) smp.q[k] = i[k] * (uint32_t)a.r;
             const int code = a.stratum[c];
             smp.x = (T) static_cast<const VT*>(a.xval)[c];
-            const T wt = pick_weight<T>(a.w, code);
+            T wt = pick_weight<T>(a.w, code);
+            if (a.weights && code != GCP_STRATUM_ZERO && code != GCP_STRATUM_SEMI_ZERO) {
+                // entry weight of a stored entry (or w_zero for an entry not
+                // stored); the zero strata's w_zero is in their stratum weight
+                const VT* __restrict__ wts = static_cast<const VT*>(a.weights);
+                Dims dm;
+#pragma unroll
+                for (int k = 0; k < D; ++k) dm.n[k] = a.n[k];
+                const uint64_t L = linear_key<D>(i, dm.n);
+                if (a.format == GCP_DENSE) {
+                    wt *= (T)wts[L];
+                } else {
+                    const int64_t e = nz_find(a.tab, L);
+                    wt *= e >= 0 ? (T)wts[e] : (T)a.w_zero;
+                }
+            }
             smp.w = code == GCP_STRATUM_NZ_CORR ? -wt : wt;
         }
         // this wave's slice; its ds operations complete in order
@@ -669,6 +688,9 @@ static GradArgs base_args(const gcp_tensor* X, const gcp_factors* M, const Scatt
     a.priv_mask = pl.priv_mask;
     a.lds_total = pl.lds_total;
     a.stage_off = pl.stage_off;
+    a.weights = X->weights;
+    a.w_zero = zero_weight(X);
+    a.kz = 1.0;
     a.acc = acc;
     a.partials = partials;
     return a;
@@ -704,6 +726,7 @@ gcp_status launch_grad_fused(gcp_loss loss, const gcp_tensor* X, const gcp_facto
     a.iter = cfg->iteration;
     a.iter_ctr = cfg->iteration_counter;
     stratum_weights(X, cfg, a.w);
+    a.kz = corr_zero_weight(X, cfg);
     a.eps = eps;
     a.loss_sum = loss_sum;
     a.adam_state = adam_state;
@@ -823,6 +846,15 @@ gcp_status launch_loss_grad(gcp_loss loss, const gcp_tensor* X, const gcp_sampli
     a.stratum = stratum;
     for (int k = 0; k < X->d; ++k) a.A[k] = M->A[k];
     stratum_weights(X, cfg, a.w);
+    a.kz = corr_zero_weight(X, cfg);
+    a.weights = X->weights;
+    a.w_zero = zero_weight(X);
+    a.format = X->format;
+    if (X->nz_table && X->nz_slots > 0) {
+        a.tab.keys = static_cast<const uint64_t*>(X->nz_table);
+        a.tab.pos = reinterpret_cast<const uint32_t*>(static_cast<const char*>(X->nz_table) + 8 * X->nz_slots);
+        a.tab.mask = (uint64_t)X->nz_slots - 1;
+    }
     a.eps = eps;
     a.ytilde = ytilde;
     a.loss_sum = loss_sum;

@@ -45,6 +45,12 @@ struct GradArgs {
     double eps;
     double* loss_sum;
     int64_t* adam_state;  // fused step: state[0] += 1 here, read by the reduction
+    // weighted objective (eq. wgcp): entry weights (type of values; NULL: all
+    // 1), the weight of entries a COO tensor does not store, and (eta/p) times
+    // it, the weight of g(0, m) in a corrected nonzero
+    const void* weights;
+    double w_zero;
+    double kz;
     // byte offset in the dynamic LDS of the per-wave sample records (64 per
     // wave, in wave order), or kNoStage when phase B broadcasts with ds_bpermute
     uint32_t stage_off;
@@ -68,19 +74,25 @@ __device__ __forceinline__ T pick_weight(const double (&w)[5], int code) {
     return (T)v;
 }
 
-// Phase A for direct items: sample c's indices, data value and stratum.
+// Phase A for direct items: sample c's indices, data value, stratum and entry
+// weight ew (eq. wgcp; 1 without weights; the zero strata's w_zero is in
+// their stratum weight).
 template <int D, typename VT, typename T>
 __device__ __forceinline__ void produce(const GradArgs& a, uint64_t iter, int64_t c, uint32_t (&i)[D], T& x,
-                                        int& code) {
+                                        int& code, T& ew) {
     const VT* __restrict__ vals = static_cast<const VT*>(a.values);
+    const VT* __restrict__ wts = static_cast<const VT*>(a.weights);
+    ew = T(1);
     if (a.sampler == GCP_SAMPLER_UNIFORM) {
         draw_index<D>(a.seed, a.pid, (uint64_t)c, iter, kPurposeUniform, a.dims.n, i);
         const uint64_t L = linear_key<D>(i, a.dims.n);
         if (a.format == GCP_DENSE) {
             x = (T)vals[L];
+            if (wts) ew = (T)wts[L];
         } else {
             const int64_t e = nz_find(a.tab, L);
             x = e >= 0 ? (T)vals[e] : T(0);
+            if (wts) ew = e >= 0 ? (T)wts[e] : (T)a.w_zero;
         }
         code = GCP_STRATUM_UNIFORM;
     } else if (c < a.p) {
@@ -88,6 +100,7 @@ __device__ __forceinline__ void produce(const GradArgs& a, uint64_t iter, int64_
 #pragma unroll
         for (int k = 0; k < D; ++k) i[k] = a.coo[e * D + k];
         x = (T)vals[e];
+        if (wts) ew = (T)wts[e];
         code = a.sampler == GCP_SAMPLER_SEMI_STRATIFIED ? GCP_STRATUM_NZ_CORR : GCP_STRATUM_NZ;
     } else {
         draw_index<D>(a.seed, a.pid, (uint64_t)(c - a.p), iter, kPurposeUniform, a.dims.n, i);
@@ -136,7 +149,8 @@ __device__ __forceinline__ Sample<D, T> no_sample() {
 }
 
 template <int D, typename T>
-__device__ __forceinline__ Sample<D, T> make_sample(const GradArgs& a, const uint32_t (&i)[D], T x, int code) {
+__device__ __forceinline__ Sample<D, T> make_sample(const GradArgs& a, const uint32_t (&i)[D], T x, int code,
+                                                    T ew = T(1)) {
     Sample<D, T> s;
 #pragma unroll
     for (int k = 0; k < D; ++k) s.q[k] = i[k];
@@ -144,7 +158,7 @@ __device__ __forceinline__ Sample<D, T> make_sample(const GradArgs& a, const uin
     if (code < 0) {
         s.w = T(0);
     } else {
-        const T w = pick_weight<T>(a.w, code);
+        const T w = pick_weight<T>(a.w, code) * ew;
         s.w = code == GCP_STRATUM_NZ_CORR ? -w : w;
     }
     return s;
@@ -224,18 +238,20 @@ __device__ __forceinline__ float quot(float x, float y) { return x * __builtin_a
 __device__ __forceinline__ double rroot(double y) { return 1.0 / sqrt(y); }
 __device__ __forceinline__ float rroot(float y) { return __builtin_amdgcn_rsqf(y); }
 
-// w * g(x, m) for the loss's derivative g (Sec. 1, 4.2 and 5.3); for a corrected
-// nonzero of semi-stratified sampling (Sec. 4.3, Alg. 3), w * (g(x, m) -
-// g(0, m)), which keeps only the part of g that depends on x.
+// w * g(x, m) for the loss's derivative g (Sec. 1, 4.2 and 5.3).  A corrected
+// nonzero of semi-stratified sampling (Sec. 4.3, Alg. 3) carries w < 0 and
+// gives |w| g(x, m) - kz g(0, m), with kz = (eta/p) w_zero; unweighted, |w| =
+// kz and this is |w| (g(x, m) - g(0, m)), only the part of g that depends on x.
 template <typename T>
-__device__ __forceinline__ T weighted_g(int loss, T x, T m, T w, T eps) {
+__device__ __forceinline__ T weighted_g(int loss, T x, T m, T w, T eps, T kz) {
     const bool corr = w < T(0);
-    T g;
+    const T aw = corr ? -w : w;
+    // g = base(m) - t(x, m): the x-free part and the part linear in x
+    T base, t;
     if (loss == GCP_LOSS_GAUSSIAN) {
-        g = corr ? T(-2) * x : T(2) * (m - x);
+        base = T(2) * m;
+        t = T(2) * x;
     } else {
-        // g = base(m) - t(x, m): the x-free part and the part linear in x
-        T base, t;
         if (loss == GCP_LOSS_GAMMA) {
             const T u = quot(T(1), m + eps);
             base = u;
@@ -248,9 +264,20 @@ __device__ __forceinline__ T weighted_g(int loss, T x, T m, T w, T eps) {
             t = quot(x, m + eps);
             base = loss == GCP_LOSS_BERNOULLI_ODDS ? quot(T(1), m + T(1)) : T(1);
         }
-        g = corr ? -t : base - t;
     }
-    return (corr ? -w : w) * g;
+    // corrected: (|w| - kz) base - |w| t, exact cancellation when unweighted
+    return corr ? (aw - kz) * base - aw * t : aw * (base - t);
+}
+
+// The weighted loss term matching weighted_g: w f(x, m), or for a corrected
+// nonzero |w| f(x, m) - kz f(0, m), written so that it is exactly
+// |w| (f(x, m) - f(0, m)) when unweighted.
+template <typename T>
+__device__ __forceinline__ T weighted_f(int loss, T x, T m, T w, T eps, T kz) {
+    if (w >= T(0)) return w * loss_f<T>(loss, x, m, eps);
+    const T aw = -w;
+    const T f0 = loss_f<T>(loss, T(0), m, eps);
+    return aw * (loss_f<T>(loss, x, m, eps) - f0) + (aw - kz) * f0;
 }
 
 // Element of a factor block through a buffer resource (32-bit byte offset).
@@ -296,6 +323,7 @@ struct PhaseB {
     int lps, spw, slot, r, loss;
     uint32_t j, priv;
     bool colj;
+    double kz;
     __amdgpu_buffer_rsrc_t rs[D];
     uint32_t lbase[D];
     double* accj[D];
@@ -355,13 +383,8 @@ __device__ __forceinline__ void pass_batches(const GradArgs& a, const PhaseB<D, 
                 y = xx[u];
             } else {
                 const T m = group_sum(pre[D - 1] * av[u][D - 1], b.lps);
-                y = weighted_g(b.loss, xx[u], m, ww[u], eps);
-                if (a.loss_sum && live && b.j == 0) {
-                    const bool corr = ww[u] < T(0);
-                    T f = loss_f<T>(b.loss, xx[u], m, eps);
-                    if (corr) f -= loss_f<T>(b.loss, T(0), m, eps);
-                    fsum += (corr ? -ww[u] : ww[u]) * f;
-                }
+                y = weighted_g(b.loss, xx[u], m, ww[u], eps, (T)b.kz);
+                if (a.loss_sum && live && b.j == 0) fsum += weighted_f(b.loss, xx[u], m, ww[u], eps, (T)b.kz);
             }
             if (live && b.colj) {
 #pragma unroll
@@ -404,6 +427,7 @@ __device__ __forceinline__ void evaluate_and_scatter(const GradArgs& a, LT* __re
     b.loss = uni((int32_t)a.loss);
     b.priv = uni(a.priv_mask);
     b.colj = (int)b.j < b.r;
+    b.kz = a.kz;
     double* const acc = uni(a.acc);
 #pragma unroll
     for (int k = 0; k < D; ++k) {

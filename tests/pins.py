@@ -66,11 +66,14 @@ def full_model(A):
     return np.einsum(",".join(f"{c}z" for c in letters) + "->" + letters, *A)
 
 
-def exact_gradient(loss, X, A, eps=oracle.LOSS_EPS):
-    """G_k = Y_(k) Z_k (eqs. Y, Gk) with explicit unfolding and Khatri-Rao product."""
+def exact_gradient(loss, X, A, eps=oracle.LOSS_EPS, W=None):
+    """G_k = Y_(k) Z_k (eqs. Y, Gk) with explicit unfolding and Khatri-Rao
+    product; with entry weights W, y_i = w_i g(x_i, m_i) (eq. wgcp)."""
     M = full_model(A)
     gvec = np.vectorize(lambda x, m: oracle.loss_g(loss, float(x), float(m), eps))
     Y = gvec(X, M)
+    if W is not None:
+        Y = Y * W
     G = []
     for k in range(len(A)):
         Z = khatri_rao([A[j] for j in range(len(A)) if j != k])
@@ -369,6 +372,97 @@ def pin_unbiased(sampler, loss, N=2000):
     return dev <= 3.0 * tr / N, f"||mean-g||^2={dev:.4g} bound={3.0 * tr / N:.4g}"
 
 
+def _weighted_case(seed=61):
+    """Tiny counts tensor with a weight per stored entry and w_zero for the rest."""
+    X, coo, val, A = tiny_sparse("counts", seed=seed)
+    rng = np.random.default_rng(seed)
+    coo_w = rng.uniform(0.2, 2.0, size=coo.shape[0])
+    w_zero = 0.3
+    W = np.full(X.shape, w_zero)
+    for e in range(coo.shape[0]):
+        W[tuple(int(t) for t in coo[e])] = coo_w[e]
+    return X, coo, val, A, coo_w, w_zero, W
+
+
+def pin_weighted_unbiased(sampler, N=2000):
+    """Weighted GCP (eq. wgcp): every sampler's estimate, with entry weights
+    folded into ytilde, is unbiased for the exact weighted gradient
+    Y_(k) Z_k with y_i = w_i g(x_i, m_i) (per-entry weights on stored
+    entries, w_zero elsewhere; dense: a weight per entry)."""
+    loss = oracle.POISSON
+    if sampler == oracle.UNIFORM:
+        X, A = tiny_dense((4, 3, 5), r=2)
+        X = np.round(np.abs(X))
+        A = [np.abs(a) + 0.1 for a in A]
+        W = np.random.default_rng(62).uniform(0.0, 2.0, size=X.shape)
+        data, wkw = dict(dense=X), dict(dense_w=W)
+        nnz = 0
+    else:
+        X, coo, val, A, coo_w, w_zero, W = _weighted_case()
+        data, wkw = dict(coo_idx=coo, coo_val=val), dict(coo_idx=coo, coo_w=coo_w, w_zero=w_zero)
+        nnz = coo.shape[0]
+    dims = X.shape
+    Gx = np.concatenate([g.reshape(-1) for g in exact_gradient(loss, X, A, W=W)])
+    # enough samples per draw that a wrong weight on the corrected terms
+    # (a fixed bias) stands out of the 3 tr(Sigma)/N band
+    s, p, q = 40, 60, 80
+
+    def draw(t):
+        smp = oracle.sample(sampler, dims, s=s, p=p, q=q, seed=37, iteration=t, **data)
+        wg = oracle.entry_weights(dims, smp, **wkw)
+        G, _ = oracle.grad(loss, dims, A, smp, nnz=nnz, s=s, p=p, q=q, wgt=wg, w_zero=wkw.get("w_zero", 1.0))
+        return G
+
+    mean, tr = _mean_and_trace(draw, N)
+    dev = float(np.sum((mean - Gx) ** 2))
+    return dev <= 3.0 * tr / N, f"||mean-g||^2={dev:.4g} bound={3.0 * tr / N:.4g}"
+
+
+def pin_weighted_ones_is_unweighted():
+    """All weights 1 (stored entries and w_zero) give the unweighted estimate
+    exactly, for the corrected semi-stratified terms too."""
+    X, coo, val, A = tiny_sparse("counts")
+    dims = X.shape
+    for sampler in (oracle.STRATIFIED, oracle.SEMI_STRATIFIED):
+        smp = oracle.sample(sampler, dims, coo_idx=coo, coo_val=val, p=9, q=11, seed=5)
+        wg = oracle.entry_weights(dims, smp, coo_idx=coo, coo_w=np.ones(coo.shape[0]), w_zero=1.0)
+        G1, F1 = oracle.grad(oracle.POISSON, dims, A, smp, nnz=coo.shape[0], p=9, q=11, wgt=wg, w_zero=1.0)
+        G0, F0 = oracle.grad(oracle.POISSON, dims, A, smp, nnz=coo.shape[0], p=9, q=11)
+        if F1 != F0 or any(not np.array_equal(a, b) for a, b in zip(G1, G0)):
+            return False, f"sampler {sampler}"
+    return True, "ok"
+
+
+def pin_missing_data(N=3000):
+    """Missing entries (Sec. 4.4): zero weights on a dense tensor's missing
+    entries under uniform sampling, and nonzero picks over the list of observed
+    entries (observed zeros stored explicitly, q = 0), both estimate the
+    gradient of the loss over the observed entries only."""
+    X, A = tiny_dense((4, 3, 5), r=2)
+    rng = np.random.default_rng(71)
+    mask = (rng.random(X.shape) < 0.6).astype(float)
+    dims = X.shape
+    Gx = np.concatenate([g.reshape(-1) for g in exact_gradient(oracle.GAUSSIAN, X, A, W=mask)])
+    obs = np.argwhere(mask > 0)
+    obs_val = X[tuple(obs.T)]
+
+    def draw_uniform(t):
+        smp = oracle.sample(oracle.UNIFORM, dims, dense=X, s=20, seed=41, iteration=t)
+        wg = oracle.entry_weights(dims, smp, dense_w=mask)
+        return oracle.grad(oracle.GAUSSIAN, dims, A, smp, s=20, wgt=wg)[0]
+
+    def draw_observed(t):
+        smp = oracle.sample(oracle.STRATIFIED, dims, coo_idx=obs, coo_val=obs_val, p=20, q=0, seed=43, iteration=t)
+        return oracle.grad(oracle.GAUSSIAN, dims, A, smp, nnz=obs.shape[0], p=20, q=0)[0]
+
+    for draw, name in ((draw_uniform, "zero weights"), (draw_observed, "observed list")):
+        mean, tr = _mean_and_trace(draw, N)
+        dev = float(np.sum((mean - Gx) ** 2))
+        if not dev <= 3.0 * tr / N:
+            return False, f"{name}: ||mean-g||^2={dev:.4g} bound={3.0 * tr / N:.4g}"
+    return True, "ok"
+
+
 def pin_semi_zero_half_poisson(N=2000):
     """P6: with p = 0 the semi-stratified estimate for Poisson (g(0,m) = 1) has
     expectation the all-ones MTTKRP, 1 (hadamard_{j != k} 1^T A_j)."""
@@ -566,6 +660,11 @@ ALL_PINS = {
     "fd_poisson_semi": lambda: pin_finite_differences(oracle.POISSON),
     "fd_gamma_uniform": lambda: pin_finite_differences(oracle.GAMMA),
     "fd_beta_half_semi": lambda: pin_finite_differences(oracle.BETA_HALF),
+    "weighted_unbiased_uniform": lambda: pin_weighted_unbiased(oracle.UNIFORM),
+    "weighted_unbiased_stratified": lambda: pin_weighted_unbiased(oracle.STRATIFIED),
+    "weighted_unbiased_semi": lambda: pin_weighted_unbiased(oracle.SEMI_STRATIFIED),
+    "weighted_ones_is_unweighted": pin_weighted_ones_is_unweighted,
+    "missing_data": pin_missing_data,
     "cp_score": pin_cp_score,
     "adam_fit_recovers": pin_adam_fit_recovers,
     "adam_fit_undo": pin_adam_fit_undo,

@@ -37,7 +37,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_struct_layouts_match_header():
     m = _lib()
-    assert ctypes.sizeof(m.GcpTensor) == 128
+    assert ctypes.sizeof(m.GcpTensor) == 144
     assert ctypes.sizeof(m.GcpFactors) == 80
     assert ctypes.sizeof(m.GcpSampling) == 72
     assert ctypes.sizeof(m.GcpFitOptions) == 208

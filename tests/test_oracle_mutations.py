@@ -4,7 +4,8 @@ Mutations (planted inside the oracle only, switched by a test hook):
 1 Gaussian derivative sign flipped; 2 stratified zeros not rejected;
 3 semi-stratified "zero" weight zeta/q instead of omega/q; 4 semi-stratified
 nonzero correction -g(0,m) dropped; 5 the wrong factor left out of the
-Khatri-Rao row; 6 Adam epsilon moved outside the square root.
+Khatri-Rao row; 6 Adam epsilon moved outside the square root; 7 weighted
+semi-stratified correction uses the entry's own weight instead of w_zero.
 """
 import pytest
 
@@ -18,6 +19,7 @@ EXPECTED = {
     4: {"unbiased_semi_bernoulli", "fd_poisson_semi"},
     5: {"enumeration_equals_unfolding", "gaussian_closed_form", "poisson_closed_form"},
     6: {"adam_closed_forms"},
+    7: {"weighted_unbiased_semi"},
 }
 
 
