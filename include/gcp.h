@@ -81,12 +81,15 @@ typedef enum gcp_loss {
  * omega/s); STRATIFIED (Sec. 4.2, Alg. 2; p nonzeros with weight eta/p, q zeros
  * by rejection with weight zeta/q); SEMI_STRATIFIED (Sec. 4.3, Alg. 3; p
  * nonzeros with weight eta/p and derivative g(x,m) - g(0,m), q uniform
- * "zeros" with x := 0 and weight omega/q).  omega = prod n_k, eta = nnz,
- * zeta = omega - eta. */
+ * "zeros" with x := 0 and weight omega/q); FULL (every entry once, sample c
+ * being entry c in row-major order, weight 1: the exact, non-stochastic
+ * gradient and loss of eqs. gcp, Y, Gk; s, p, q unused; a COO tensor needs
+ * nz_table).  omega = prod n_k, eta = nnz, zeta = omega - eta. */
 typedef enum gcp_sampler {
     GCP_SAMPLER_UNIFORM = 0,
     GCP_SAMPLER_STRATIFIED = 1,
-    GCP_SAMPLER_SEMI_STRATIFIED = 2
+    GCP_SAMPLER_SEMI_STRATIFIED = 2,
+    GCP_SAMPLER_FULL = 3
 } gcp_sampler;
 
 /* Per-sample stratum codes written by gcp_sample and read by gcp_loss_grad.

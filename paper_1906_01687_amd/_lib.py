@@ -17,7 +17,7 @@ GCP_MAX_RANK = 64
 # enums (include/gcp.h)
 F32, F64, BF16 = 0, 1, 2
 GAUSSIAN, BERNOULLI_ODDS, POISSON, GAMMA, BETA_HALF = 0, 1, 2, 3, 4
-UNIFORM, STRATIFIED, SEMI_STRATIFIED = 0, 1, 2
+UNIFORM, STRATIFIED, SEMI_STRATIFIED, FULL = 0, 1, 2, 3
 STRATUM_UNIFORM, STRATUM_NZ, STRATUM_ZERO, STRATUM_NZ_CORR, STRATUM_SEMI_ZERO = 0, 1, 2, 3, 4
 DENSE, COO = 0, 1
 EPS_INSIDE_SQRT, EPS_OUTSIDE_SQRT = 0, 1

@@ -20,7 +20,8 @@ from ._lib import (BF16, COO, DENSE, F32, F64, GcpFactors, GcpSampling, GcpTenso
 
 LOSSES = {"gaussian": _lib.GAUSSIAN, "bernoulli_odds": _lib.BERNOULLI_ODDS, "poisson": _lib.POISSON,
           "gamma": _lib.GAMMA, "beta_half": _lib.BETA_HALF}
-SAMPLERS = {"uniform": _lib.UNIFORM, "stratified": _lib.STRATIFIED, "semi_stratified": _lib.SEMI_STRATIFIED}
+SAMPLERS = {"uniform": _lib.UNIFORM, "stratified": _lib.STRATIFIED, "semi_stratified": _lib.SEMI_STRATIFIED,
+            "full": _lib.FULL}
 LOSS_EPS = 1e-10
 
 _TORCH_DTYPE = {F32: torch.float32, F64: torch.float64, BF16: torch.bfloat16}
@@ -215,7 +216,12 @@ def sampling(sampler="uniform", s=0, p=0, q=0, seed=0, problem_id=0, iteration=0
     return c
 
 
-def n_samples(cfg: GcpSampling) -> int:
+def n_samples(cfg: GcpSampling, X: Optional["DataTensor"] = None) -> int:
+    """Samples one draw yields (FULL: every entry of X)."""
+    if cfg.sampler == _lib.FULL:
+        if X is None:
+            raise ValueError("the FULL sampler's sample count needs the tensor")
+        return X.omega
     return cfg.s if cfg.sampler == _lib.UNIFORM else cfg.p + cfg.q
 
 
@@ -231,7 +237,7 @@ def sample(X: DataTensor, cfg: GcpSampling, stream=None):
     """gcp_sample: (idx [S, d] int32, xval [S], stratum [S] uint8)."""
     L = lib()
     dev = X.values.device
-    S = n_samples(cfg)
+    S = n_samples(cfg, X)
     idx = torch.empty((max(S, 1), X.d), dtype=torch.int32, device=dev)
     xval = torch.empty(max(S, 1), dtype=X.values.dtype, device=dev)
     st = torch.empty(max(S, 1), dtype=torch.uint8, device=dev)

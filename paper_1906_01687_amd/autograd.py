@@ -60,7 +60,7 @@ class SampledLoss:
         self.loss = _loss_code(loss)
         self.X, self.M, self.cfg, self.eps = X, M, cfg, float(eps)
         self.t, self.m = X.struct(), M.struct()
-        self.S = n_samples(cfg)
+        self.S = n_samples(cfg, X)
         dev = X.values.device
         self.dev = dev
         self.sample_bytes = int(L.gcp_sample_workspace_bytes(ctypes.byref(self.t), ctypes.byref(cfg)))

@@ -50,7 +50,7 @@ static double omega_d(const gcp_tensor* X) {
 void stratum_weights(const gcp_tensor* X, const gcp_sampling* cfg, double w[5]) {
     const double omega = omega_d(X);
     const double eta = (double)X->nnz;
-    w[GCP_STRATUM_UNIFORM] = cfg->s > 0 ? omega / (double)cfg->s : 0.0;
+    w[GCP_STRATUM_UNIFORM] = cfg->sampler == GCP_SAMPLER_FULL ? 1.0 : (cfg->s > 0 ? omega / (double)cfg->s : 0.0);
     w[GCP_STRATUM_NZ] = cfg->p > 0 ? eta / (double)cfg->p : 0.0;
     w[GCP_STRATUM_ZERO] = cfg->q > 0 ? (omega - eta) / (double)cfg->q : 0.0;
     w[GCP_STRATUM_NZ_CORR] = w[GCP_STRATUM_NZ];
@@ -72,6 +72,8 @@ double corr_zero_weight(const gcp_tensor* X, const gcp_sampling* cfg) {
     stratum_weights(X, cfg, w);
     return w[GCP_STRATUM_NZ_CORR] * zero_weight(X);
 }
+
+int64_t full_count(const gcp_tensor* X) { return (int64_t)omega128(X); }
 
 int64_t rejection_batch(const gcp_tensor* X, const gcp_sampling* cfg) {
     const double omega = omega_d(X);
@@ -153,6 +155,11 @@ static gcp_status check_table(const gcp_tensor* X) {
 static gcp_status check_sampling(const gcp_tensor* X, const gcp_sampling* cfg) {
     if (!cfg) return set_error(GCP_ERR_INVALID_ARG, "cfg is NULL");
     switch (cfg->sampler) {
+    case GCP_SAMPLER_FULL:
+        if (X->format == GCP_COO && X->nnz > 0) {
+            if (gcp_status st = check_table(X)) return st;
+        }
+        break;
     case GCP_SAMPLER_UNIFORM:
         if (cfg->s < 0) return set_error(GCP_ERR_INVALID_ARG, "cfg->s must be >= 0");
         if (X->format == GCP_COO && cfg->s > 0) {
@@ -205,7 +212,8 @@ static gcp_status check_loss(gcp_loss loss) {
     return GCP_OK;
 }
 
-static int64_t sample_count(const gcp_sampling* cfg) {
+static int64_t sample_count(const gcp_tensor* X, const gcp_sampling* cfg) {
+    if (cfg->sampler == GCP_SAMPLER_FULL) return full_count(X);
     return cfg->sampler == GCP_SAMPLER_UNIFORM ? cfg->s : cfg->p + cfg->q;
 }
 
@@ -261,7 +269,7 @@ static size_t fused_ws(const gcp_tensor* X, const gcp_factors* M, const gcp_samp
     FusedLayout f{};
     f.rejection = cfg->sampler == GCP_SAMPLER_STRATIFIED && cfg->q > 0;
     f.ncand = f.rejection ? rejection_batch(X, cfg) : 0;
-    f.plan = plan_scatter(X, M, fused_items(cfg, f.ncand));
+    f.plan = plan_scatter(X, M, fused_items(X, cfg, f.ncand));
     Carver c;
     f.acc = c.take<double>(base, (size_t)f.plan.acc_total);
     f.partials = c.take<char>(base, scatter_partials_bytes(f.plan, M->dtype));
@@ -402,7 +410,7 @@ gcp_status gcp_sample(const gcp_tensor* X, const gcp_sampling* cfg, uint32_t* id
     clear_error();
     if (gcp_status st = check_tensor(X)) return st;
     if (gcp_status st = check_sampling(X, cfg)) return st;
-    const int64_t S = sample_count(cfg);
+    const int64_t S = sample_count(X, cfg);
     if (S == 0) return launch_bump_counter(cfg->iteration_counter, stream);
     if (!idx || !xval || !stratum) return set_error(GCP_ERR_INVALID_ARG, "idx, xval and stratum must be non-NULL");
     Carver c;
@@ -410,9 +418,9 @@ gcp_status gcp_sample(const gcp_tensor* X, const gcp_sampling* cfg, uint32_t* id
     const size_t need = sample_ws(X, cfg, c, ws, &rs);
     if (need > 0 && (!ws || ws_bytes < need))
         return set_error(GCP_ERR_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
-    if (cfg->sampler == GCP_SAMPLER_UNIFORM) {
-        if (gcp_status st = launch_sample_direct(X, cfg, kKindUniform, cfg->s, 0, idx, xval, stratum, stream))
-            return st;
+    if (cfg->sampler == GCP_SAMPLER_UNIFORM || cfg->sampler == GCP_SAMPLER_FULL) {
+        const int kind = cfg->sampler == GCP_SAMPLER_FULL ? kKindFull : kKindUniform;
+        if (gcp_status st = launch_sample_direct(X, cfg, kind, S, 0, idx, xval, stratum, stream)) return st;
     } else {
         if (gcp_status st = launch_sample_direct(X, cfg, kKindNonzero, cfg->p, 0, idx, xval, stratum, stream))
             return st;
@@ -607,7 +615,8 @@ size_t fit_layout(const gcp_tensor* X, const gcp_factors* M, const gcp_fit_optio
     f.esz = M->dtype == GCP_F64 ? 8 : (M->dtype == GCP_F32 ? 4 : 2);
     f.msz = M->dtype == GCP_F64 ? 8 : 4;
     const size_t vsz = X->vdtype == GCP_F64 ? 8 : 4;
-    f.S_est = opt->est.sampler == GCP_SAMPLER_UNIFORM ? opt->est.s : opt->est.p + opt->est.q;
+    f.S_est = opt->est.sampler == GCP_SAMPLER_FULL ? full_count(X)
+              : (opt->est.sampler == GCP_SAMPLER_UNIFORM ? opt->est.s : opt->est.p + opt->est.q);
     gcp_sampling grad = opt->grad;
     grad.iteration_counter = nullptr;
     gcp_sampling est = opt->est;

@@ -308,8 +308,8 @@ gcp_status batch_create(const gcp_problem* problems, int32_t count, const gcp_ba
             a.tab.mask = (uint64_t)pr.X.nz_slots - 1;
         }
         a.tab.bitmap = pr.X.nz_bitmap;
-        if (pr.cfg.sampler == GCP_SAMPLER_UNIFORM) {
-            a.n_direct = pr.cfg.s;
+        if (pr.cfg.sampler == GCP_SAMPLER_UNIFORM || pr.cfg.sampler == GCP_SAMPLER_FULL) {
+            a.n_direct = pr.cfg.sampler == GCP_SAMPLER_FULL ? full_count(&pr.X) : pr.cfg.s;
             a.p = 0;
         } else {
             a.n_direct = pr.cfg.p + pr.cfg.q;

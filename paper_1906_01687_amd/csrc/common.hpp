@@ -108,7 +108,7 @@ struct ScatterPlan {
 };
 ScatterPlan plan_scatter(const gcp_tensor* X, const gcp_factors* M, int64_t n_items);
 size_t scatter_partials_bytes(const ScatterPlan& pl, int fdtype);
-int64_t fused_items(const gcp_sampling* cfg, int64_t ncand);
+int64_t fused_items(const gcp_tensor* X, const gcp_sampling* cfg, int64_t ncand);
 
 struct AdamParams {
     void* A;
@@ -125,7 +125,7 @@ gcp_status launch_nz_build(const gcp_tensor* X, void* table, int64_t slots, hipS
 gcp_status launch_nz_bitmap(const gcp_tensor* X, uint32_t* bitmap, size_t bytes, hipStream_t s);
 
 // Direct samples c in [0, count) of one kind, written at out_off.
-enum SampleKind { kKindUniform = 0, kKindNonzero = 1, kKindSemiZero = 2 };
+enum SampleKind { kKindUniform = 0, kKindNonzero = 1, kKindSemiZero = 2, kKindFull = 3 };
 gcp_status launch_sample_direct(const gcp_tensor* X, const gcp_sampling* cfg, int kind,
                                 int64_t count, int64_t out_off, uint32_t* idx, void* xval,
                                 uint8_t* stratum, hipStream_t s);
@@ -145,6 +145,7 @@ gcp_status launch_bump_counter(uint64_t* counter, hipStream_t s);
 // Stratum weights for X and cfg (omega/s, eta/p, zeta/q, eta/p, omega/q).
 void stratum_weights(const gcp_tensor* X, const gcp_sampling* cfg, double w[5]);
 double zero_weight(const gcp_tensor* X);
+int64_t full_count(const gcp_tensor* X);  // entries of X (the FULL sampler's sample count)
 double corr_zero_weight(const gcp_tensor* X, const gcp_sampling* cfg);
 
 gcp_status launch_loss_grad(gcp_loss loss, const gcp_tensor* X, const gcp_sampling* cfg,

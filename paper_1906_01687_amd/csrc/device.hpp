@@ -1,6 +1,6 @@
 // device.hpp -- device helpers of libgcp (gfx950, wave64).
 //
-// Philox4x64-10 counter-based draws, randi, the three losses, bf16 storage and
+// Philox4x64-10 counter-based draws, randi, the five losses, bf16 storage and
 // the nonzero hash probe.  Everything here is __device__ code used by the
 // sampling and gradient kernels.
 #pragma once
@@ -81,6 +81,18 @@ __device__ __forceinline__ uint64_t draw_nonzero(uint64_t seed, uint64_t pid, ui
 }
 
 template <int D>
+__device__ __forceinline__ void unravel(uint64_t L, const int64_t* __restrict__ dims, uint32_t (&i)[D]) {
+    // row-major: the last mode varies fastest
+#pragma unroll
+    for (int k = D - 1; k > 0; --k) {
+        const uint64_t n = (uint64_t)dims[k];
+        i[k] = (uint32_t)(L % n);
+        L /= n;
+    }
+    i[0] = (uint32_t)L;
+}
+
+template <int D>
 __device__ __forceinline__ uint64_t linear_key(const uint32_t (&i)[D], const int64_t* __restrict__ dims) {
     uint64_t L = 0;
 #pragma unroll
@@ -117,6 +129,13 @@ __device__ __forceinline__ int64_t nz_find(const NzTable& t, uint64_t L) {
         h = (h + 1) & t.mask;
     }
     return -1;
+}
+
+// COO position of linear key L, or -1: the bitmap (when present) answers
+// "not stored" with one load, so only stored entries walk the hash.
+__device__ __forceinline__ int64_t nz_lookup(const NzTable& t, uint64_t L) {
+    if (t.bitmap && !((t.bitmap[L >> 5] >> (L & 31)) & 1u)) return -1;
+    return nz_find(t, L);
 }
 
 // Whether X is nonzero at linear key L: one bitmap load when the bitmap

@@ -707,8 +707,9 @@ gcp_status launch_grad_list(const gcp_tensor* X, const gcp_factors* M, const uin
     return check_launch("gcp_mttkrp");
 }
 
-int64_t fused_items(const gcp_sampling* cfg, int64_t ncand) {
+int64_t fused_items(const gcp_tensor* X, const gcp_sampling* cfg, int64_t ncand) {
     if (cfg->sampler == GCP_SAMPLER_UNIFORM) return (cfg->s + kWave - 1) / kWave;
+    if (cfg->sampler == GCP_SAMPLER_FULL) return (full_count(X) + kWave - 1) / kWave;
     if (cfg->sampler == GCP_SAMPLER_SEMI_STRATIFIED) return (cfg->p + cfg->q + kWave - 1) / kWave;
     const int64_t zero_items = cfg->q > 0 ? (ncand + kWave - 1) / kWave : 0;
     return (cfg->p + kWave - 1) / kWave + zero_items;
@@ -730,8 +731,8 @@ gcp_status launch_grad_fused(gcp_loss loss, const gcp_tensor* X, const gcp_facto
     a.eps = eps;
     a.loss_sum = loss_sum;
     a.adam_state = adam_state;
-    if (cfg->sampler == GCP_SAMPLER_UNIFORM) {
-        a.n_direct = cfg->s;
+    if (cfg->sampler == GCP_SAMPLER_UNIFORM || cfg->sampler == GCP_SAMPLER_FULL) {
+        a.n_direct = cfg->sampler == GCP_SAMPLER_FULL ? full_count(X) : cfg->s;
         a.p = 0;
     } else if (cfg->sampler == GCP_SAMPLER_SEMI_STRATIFIED) {
         a.n_direct = cfg->p + cfg->q;

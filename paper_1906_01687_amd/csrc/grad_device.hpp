@@ -83,14 +83,21 @@ __device__ __forceinline__ void produce(const GradArgs& a, uint64_t iter, int64_
     const VT* __restrict__ vals = static_cast<const VT*>(a.values);
     const VT* __restrict__ wts = static_cast<const VT*>(a.weights);
     ew = T(1);
-    if (a.sampler == GCP_SAMPLER_UNIFORM) {
-        draw_index<D>(a.seed, a.pid, (uint64_t)c, iter, kPurposeUniform, a.dims.n, i);
-        const uint64_t L = linear_key<D>(i, a.dims.n);
+    if (a.sampler == GCP_SAMPLER_UNIFORM || a.sampler == GCP_SAMPLER_FULL) {
+        uint64_t L;
+        if (a.sampler == GCP_SAMPLER_FULL) {
+            // sample c is entry c
+            L = (uint64_t)c;
+            unravel<D>(L, a.dims.n, i);
+        } else {
+            draw_index<D>(a.seed, a.pid, (uint64_t)c, iter, kPurposeUniform, a.dims.n, i);
+            L = linear_key<D>(i, a.dims.n);
+        }
         if (a.format == GCP_DENSE) {
             x = (T)vals[L];
             if (wts) ew = (T)wts[L];
         } else {
-            const int64_t e = nz_find(a.tab, L);
+            const int64_t e = nz_lookup(a.tab, L);
             x = e >= 0 ? (T)vals[e] : T(0);
             if (wts) ew = e >= 0 ? (T)wts[e] : (T)a.w_zero;
         }

@@ -95,13 +95,14 @@ __global__ void sample_direct_kernel(DirectArgs a) {
             x = vals[e];
             code = a.nz_code;
         } else {
-            draw_index<D>(a.seed, a.pid, (uint64_t)c, iter, kPurposeUniform, a.dims.n, i);
-            if (a.kind == kKindUniform) {
+            if (a.kind == kKindFull) unravel<D>((uint64_t)c, a.dims.n, i);
+            else draw_index<D>(a.seed, a.pid, (uint64_t)c, iter, kPurposeUniform, a.dims.n, i);
+            if (a.kind == kKindUniform || a.kind == kKindFull) {
                 const uint64_t L = linear_key<D>(i, a.dims.n);
                 if (a.format == GCP_DENSE) {
                     x = vals[L];
                 } else {
-                    const int64_t e = nz_find(a.tab, L);
+                    const int64_t e = nz_lookup(a.tab, L);
                     x = e >= 0 ? vals[e] : VT(0);
                 }
                 code = GCP_STRATUM_UNIFORM;

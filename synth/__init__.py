@@ -321,6 +321,87 @@ def dense_gaussian_200x200x200x200(dtype="f32", s=1_000_000) -> Workload:
                     seed=4003, lr=1e-3)
 
 
+def sparse_binary_appd(dims, rank, delta=0.15, p_high=0.9, p_low=0.002, seed=0):
+    """Binary test problem of the paper's App. D (odds link): components 1..r-1
+    have sparse factor columns (each entry nonzero with probability delta,
+    value |N(c_high, 0.5)| with c_high = (p_high / (1 - p_high))^(1/d)); the
+    last component is dense with every entry c_low = (p_low / (1 - p_low))^(1/d),
+    so away from the sparse components a one has probability p_low.  Entries
+    inside some sparse component's support get their exact probability
+    m/(1+m) and one Bernoulli draw each; the p_low ones elsewhere are drawn in
+    bulk (a binomial count of distinct uniform keys outside those supports).
+    Returns (coo_idx uint32 [nnz, d] sorted by linear key, values ones, A_true)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d = len(dims)
+    dims = tuple(int(n) for n in dims)
+    c_high = (p_high / (1.0 - p_high)) ** (1.0 / d)
+    c_low = (p_low / (1.0 - p_low)) ** (1.0 / d)
+    A = []
+    for n in dims:
+        a = np.zeros((n, rank))
+        for j in range(rank - 1):
+            hit = rng.random(n) < delta
+            a[hit, j] = np.abs(rng.normal(c_high, 0.5, size=int(hit.sum())))
+        a[:, rank - 1] = c_low
+        A.append(a)
+    strides = np.ones(d, dtype=np.int64)
+    for k in range(d - 2, -1, -1):
+        strides[k] = strides[k + 1] * dims[k + 1]
+    keys = []
+    for j in range(rank - 1):
+        sup = [np.nonzero(A[k][:, j])[0].astype(np.int64) for k in range(d)]
+        grid = np.zeros(1, dtype=np.int64)
+        for k in range(d):
+            grid = (grid[:, None] + (sup[k] * strides[k])[None, :]).reshape(-1)
+        keys.append(grid)
+    cand = np.unique(np.concatenate(keys)) if keys else np.zeros(0, dtype=np.int64)
+    idx = np.stack([(cand // strides[k]) % dims[k] for k in range(d)], axis=1)
+    m = np.full(cand.shape[0], c_low ** d)
+    for j in range(rank - 1):
+        prod = np.ones(cand.shape[0])
+        for k in range(d):
+            prod *= A[k][idx[:, k], j]
+        m += prod
+    ones_c = cand[rng.random(cand.shape[0]) < m / (1.0 + m)]
+    omega = int(np.prod(np.array(dims, dtype=object)))
+    n_noise = int(rng.binomial(omega - cand.shape[0], p_low))
+    noise = np.zeros(0, dtype=np.int64)
+    while noise.shape[0] < n_noise:
+        draw = rng.integers(0, omega, size=(n_noise - noise.shape[0]) * 11 // 10 + 16, dtype=np.int64)
+        draw = draw[~np.isin(draw, cand)]
+        noise = np.unique(np.concatenate([noise, draw]))
+    noise = rng.permutation(noise)[:n_noise]
+    nz = np.sort(np.concatenate([ones_c, noise]))
+    coo = np.stack([(nz // strides[k]) % dims[k] for k in range(d)], axis=1).astype(np.uint32)
+    return coo, np.ones(coo.shape[0]), A
+
+
+def sparse_binary_400x300x200x100(cache=True):
+    """The sampler-comparison tensor of the paper's Sec. 5.4 (Table 1): App. D
+    recipe with delta = 0.15, p_high = 0.9, p_low = 0.002, rank 5."""
+    dims, r = (400, 300, 200, 100), 5
+
+    def make():
+        coo, val, A = sparse_binary_appd(dims, r, 0.15, 0.9, 0.002, seed=7001)
+        out = {"coo": coo, "val": val}
+        for k, a in enumerate(A):
+            out[f"A{k}"] = a
+        return out
+
+    z = _cached(f"appd:{dims}:{r}:7001:v1", make) if cache else make()
+    A_true = [z[f"A{k}"] for k in range(len(dims))]
+    rng = np.random.Generator(np.random.PCG64(7002))
+    nnz = z["coo"].shape[0]
+    omega = float(np.prod(np.array(dims, dtype=np.float64)))
+    # start: U(0,1) factors scaled so that the model's mean odds match the data's density
+    A0 = [rng.random((n, r)) for n in dims]
+    mean_m = r * 0.5 ** len(dims)
+    target = (nnz / omega) / (1.0 - nnz / omega)
+    A0 = [a * (target / mean_m) ** (1.0 / len(dims)) for a in A0]
+    return Workload("sparse_binary_400x300x200x100", dims, r, BERNOULLI_ODDS, STRATIFIED, "f32", p=500, q=500,
+                    coo_idx=z["coo"], coo_val=z["val"], A_true=A_true, A_init=A0, seed=7003, lower=0.0)
+
+
 def dense_gamma(dims, rank, seed):
     """Gamma test problem of the paper's App. C: factor entries U(0,1); every
     entry x ~ Gamma(shape 1, mean m) (exponential with mean m).  Returns
