@@ -46,6 +46,11 @@ def parse():
                     help="also time the step as SampledLoss forward + backward + Adam")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (counter calibration)")
+    ap.add_argument("--study", choices=["variance"], default=None,
+                    help="variance: the sampler comparison of Sec. 5.4 (empirical bias and variance, Table 1) "
+                         "on the 400x300x200x100 binary tensor instead of the throughput bench")
+    ap.add_argument("--draws", type=int, default=1000, help="stochastic gradients per sampler and model (study)")
+    ap.add_argument("--fit-epochs", type=int, default=60, help="GCP-Adam epoch cap for the fitted model (study)")
     return ap.parse_args()
 
 
@@ -238,6 +243,8 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.study == "variance":
+        return run_variance_study(args)
     if args.workload == "batched_64_cubes":
         return run_batched(args)
 
@@ -344,7 +351,7 @@ def main():
         "dtype": {"f64": "f64", "f32": "f32", "bf16": "bf16"}[w.dtype],
         "data": "synthetic",
         "config": {"workload": w.name, "dims": list(w.dims), "rank": w.rank, "nnz": w.nnz,
-                   "loss": ["gaussian", "bernoulli_odds", "poisson"][w.loss], "sampler": sampler_name,
+                   "loss": ["gaussian", "bernoulli_odds", "poisson", "gamma", "beta_half"][w.loss], "sampler": sampler_name,
                    "samples_per_step": samples, "p": w.p, "q": w.q, "s": w.s, "parallelism": "single_gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
@@ -355,6 +362,74 @@ def main():
     }
     if autograd is not None:
         out["autograd_step"] = autograd
+    print(json.dumps(out), flush=True)
+
+
+def run_variance_study(args):
+    """The sampler comparison of Sec. 5.4 at its full size: App. D binary tensor
+    400x300x200x100, rank 5, Bernoulli-odds loss.  At the initial guess and at a
+    GCP-Adam fit (stratified s = 1000 gradients, 200,000-entry stratified loss
+    estimate, alpha = 0.01, tau = 1000, kappa = 1, lower bound 0), N stochastic
+    gradients per sampler (uniform s = 1000; stratified and semi-stratified
+    p = q = 500) give the empirical bias ||mean - g|| and variance
+    (1/N) sum ||g_xi - mean||^2 against the exact gradient g (FULL sampler).
+    FP64 factors for the moments; one JSON line."""
+    import torch
+    import synth
+    import paper_1906_01687_amd as gcp
+    from paper_1906_01687_amd import variance
+
+    t_gen = time.time()
+    w = synth.sparse_binary_400x300x200x100()
+    dev = torch.device("cuda:0")
+    X = gcp.coo_tensor(w.dims, torch.as_tensor(np.ascontiguousarray(w.coo_idx).view(np.int32)).to(dev),
+                       torch.as_tensor(w.coo_val).float().to(dev), bitmap=True)
+    torch.cuda.synchronize()
+    print(f"[study] data {w.dims}, nnz {w.nnz} ({w.nnz / w.omega * 100:.2f}% dense), "
+          f"ready in {time.time() - t_gen:.1f} s", file=sys.stderr, flush=True)
+
+    # the fitted model: GCP-Adam from the initial guess, FP32 factors
+    Mfit = gcp.Factors(w.dims, w.rank, torch.float32, dev, init=w.A_init)
+    grad = gcp.sampling("stratified", p=500, q=500, seed=w.seed)
+    est = gcp.sampling("stratified", p=100000, q=100000, seed=w.seed + 1)
+    t0 = time.time()
+    fit = gcp.adam_fit(w.loss, X, Mfit, grad, est, lr=0.01, lower=0.0, tau=1000, kappa=1,
+                       max_epochs=args.fit_epochs)
+    torch.cuda.synchronize()
+    fit_s = time.time() - t0
+    A_fit = [a.detach().double().cpu().numpy() for a in Mfit.A]
+    score_fit = gcp.factor_match_score(w.A_true, A_fit)
+    print(f"[study] GCP-Adam: {fit.epochs} epochs in {fit_s:.1f} s, estimate {fit.history[0]:.6e} -> "
+          f"{fit.history[-1]:.6e}, score vs truth {score_fit:.3f}", file=sys.stderr, flush=True)
+
+    samplers = [("uniform", gcp.sampling("uniform", s=1000, seed=101)),
+                ("stratified", gcp.sampling("stratified", p=500, q=500, seed=102)),
+                ("semi_stratified", gcp.sampling("semi_stratified", p=500, q=500, seed=103))]
+    table = {}
+    for model, A in (("initial", w.A_init), ("fitted", A_fit), ("truth", w.A_true)):
+        M = gcp.Factors(w.dims, w.rank, torch.float64, dev, init=A)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        exact = variance.exact_gradient(w.loss, X, M)
+        torch.cuda.synchronize()
+        t_exact = time.time() - t0
+        row = {"grad_norm": float(exact.norm()), "exact_seconds": t_exact}
+        for name, cfg in samplers:
+            t0 = time.time()
+            mo = variance.gradient_moments(w.loss, X, M, cfg, args.draws, exact=exact)
+            torch.cuda.synchronize()
+            row[name] = {"bias": mo.bias, "variance": mo.variance, "seconds": time.time() - t0}
+            print(f"[study] {model:8s} {name:16s} bias {mo.bias:.3e} variance {mo.variance:.3e} "
+                  f"(||g|| {row['grad_norm']:.3e})", file=sys.stderr, flush=True)
+        table[model] = row
+        del M
+
+    out = {"study": "sampler_variance", "workload": "sparse_binary_400x300x200x100", "dims": list(w.dims),
+           "rank": w.rank, "nnz": w.nnz, "loss": "bernoulli_odds", "draws": args.draws,
+           "samples_per_gradient": 1000, "data": "synthetic (App. D recipe)",
+           "fit": {"epochs": fit.epochs, "seconds": fit_s, "estimate_first": fit.history[0],
+                   "estimate_last": fit.history[-1], "score_vs_truth": score_fit},
+           "table": table}
     print(json.dumps(out), flush=True)
 
 

@@ -38,6 +38,7 @@ from __future__ import annotations
 
 import dataclasses
 import hashlib
+import math
 import os
 from typing import List, Optional
 
@@ -321,6 +322,16 @@ def dense_gaussian_200x200x200x200(dtype="f32", s=1_000_000) -> Workload:
                     seed=4003, lr=1e-3)
 
 
+def kruskal_norm(A) -> float:
+    """Frobenius norm of the CP model [[A_1, ..., A_d]] from the Gram
+    matrices: ||M||^2 = sum over component pairs of the product over modes of
+    (A_k^T A_k)."""
+    G = np.ones((A[0].shape[1], A[0].shape[1]))
+    for a in A:
+        G *= a.T @ a
+    return float(math.sqrt(max(G.sum(), 0.0)))
+
+
 def sparse_binary_appd(dims, rank, delta=0.15, p_high=0.9, p_low=0.002, seed=0):
     """Binary test problem of the paper's App. D (odds link): components 1..r-1
     have sparse factor columns (each entry nonzero with probability delta,
@@ -390,14 +401,11 @@ def sparse_binary_400x300x200x100(cache=True):
 
     z = _cached(f"appd:{dims}:{r}:7001:v1", make) if cache else make()
     A_true = [z[f"A{k}"] for k in range(len(dims))]
+    # start (Sec. 5.4): U(0,1) factors scaled so that the model's Frobenius
+    # norm equals the data's, sqrt(nnz) for a binary tensor
     rng = np.random.Generator(np.random.PCG64(7002))
-    nnz = z["coo"].shape[0]
-    omega = float(np.prod(np.array(dims, dtype=np.float64)))
-    # start: U(0,1) factors scaled so that the model's mean odds match the data's density
     A0 = [rng.random((n, r)) for n in dims]
-    mean_m = r * 0.5 ** len(dims)
-    target = (nnz / omega) / (1.0 - nnz / omega)
-    A0 = [a * (target / mean_m) ** (1.0 / len(dims)) for a in A0]
+    A0 = [a * (math.sqrt(z["coo"].shape[0]) / kruskal_norm(A0)) ** (1.0 / len(dims)) for a in A0]
     return Workload("sparse_binary_400x300x200x100", dims, r, BERNOULLI_ODDS, STRATIFIED, "f32", p=500, q=500,
                     coo_idx=z["coo"], coo_val=z["val"], A_true=A_true, A_init=A0, seed=7003, lower=0.0)
 

@@ -283,3 +283,27 @@ def test_fit_options_are_checked():
     st = L.gcp_adam_fit(0, ctypes.byref(t), ctypes.byref(M), ctypes.byref(o), 1e-10, 0x10000, None, 0x20000,
                         0x30000, 0x40000, hist, acc, ctypes.byref(ep), None, 0x50000, 1 << 30, None)
     assert st == 1 and b"nu" in L.gcp_last_error()
+
+
+def test_factor_match_score():
+    """App. E score: 1 for the same model up to component order, column scaling
+    and sign flips in pairs of modes; low for unrelated factors; the best
+    matching is found, not a greedy one."""
+    import numpy as np
+    from paper_1906_01687_amd.score import factor_match_score
+    rng = np.random.default_rng(21)
+    A = [rng.standard_normal((n, 4)) for n in (9, 8, 7)]
+    perm = np.array([3, 1, 0, 2])
+    scale = [np.array([2.0, 0.5, 3.0, 1.0]), np.array([1.0, 4.0, 0.25, 1.0]), np.array([0.5, 0.5, 1.0, 1.0])]
+    B = [a[:, perm] * s for a, s in zip(A, scale)]
+    B[1][:, 2] *= -1
+    B[2][:, 2] *= -1
+    assert abs(factor_match_score(A, B) - 1.0) < 1e-12
+    assert factor_match_score(A, [rng.standard_normal(a.shape) for a in A]) < 0.3
+    # one mode, similarities [[0.6, 0.5], [0.5, 0.1]]: a greedy pick takes 0.6
+    # then 0.1 (mean 0.35); the best matching pairs the 0.5s (mean 0.5)
+    e = np.eye(3)
+    ref = [np.stack([e[0], e[1]], axis=1)]
+    est = [np.stack([0.6 * e[0] + 0.5 * e[1] + np.sqrt(1 - 0.61) * e[2],
+                     0.5 * e[0] + 0.1 * e[1] + np.sqrt(1 - 0.26) * e[2]], axis=1)]
+    assert abs(factor_match_score(ref, est) - 0.5) < 1e-12
