@@ -247,7 +247,7 @@ static size_t mttkrp_ws(const gcp_tensor* X, const gcp_factors* M, int64_t S, vo
                         double** acc, void** partials) {
     const ScatterPlan pl = plan_scatter(X, M, (S + 63) / 64);
     Carver c;
-    double* a = c.take<double>(base, (size_t)pl.acc_total);
+    double* a = c.take<double>(base, (size_t)acc_words(pl));
     void* p = c.take<char>(base, scatter_partials_bytes(pl, M->dtype));
     if (plan) *plan = pl;
     if (acc) *acc = a;
@@ -271,7 +271,7 @@ static size_t fused_ws(const gcp_tensor* X, const gcp_factors* M, const gcp_samp
     f.ncand = f.rejection ? rejection_batch(X, cfg) : 0;
     f.plan = plan_scatter(X, M, fused_items(X, cfg, f.ncand));
     Carver c;
-    f.acc = c.take<double>(base, (size_t)f.plan.acc_total);
+    f.acc = c.take<double>(base, (size_t)acc_words(f.plan));
     f.partials = c.take<char>(base, scatter_partials_bytes(f.plan, M->dtype));
     if (f.rejection) f.rs = carve_rejection(c, base, f.ncand, true, X->d);
     if (out) *out = f;
@@ -316,7 +316,7 @@ static gcp_status sampled_common(gcp_loss loss, const gcp_tensor* X, const gcp_f
     if (f.rejection) {
         if (gcp_status st = launch_rejection_count(X, cfg, f.ncand, f.rs, scanned, stream)) return st;
     }
-    if (gcp_status st = launch_fill_zero(f.acc, f.plan.acc_total, stream)) return st;
+    if (gcp_status st = launch_fill_zero(f.acc, acc_words(f.plan), stream)) return st;
     hipEvent_t ev0, ev1;
     timing_take(stream, &ev0, &ev1);
     if (gcp_status st = launch_grad_fused(loss, X, M, cfg, eps, f.plan, f.ncand, f.rejection ? &f.rs : nullptr,
@@ -478,7 +478,7 @@ gcp_status gcp_mttkrp(const gcp_tensor* X, const gcp_factors* M, const uint32_t*
     double* acc = nullptr;
     void* partials = nullptr;
     mttkrp_ws(X, M, S, ws, &pl, &acc, &partials);
-    if (gcp_status st = launch_fill_zero(acc, pl.acc_total, stream)) return st;
+    if (gcp_status st = launch_fill_zero(acc, acc_words(pl), stream)) return st;
     if (gcp_status st = launch_grad_list(X, M, idx, ytilde, S, pl, acc, partials, stream)) return st;
     return launch_reduce(M, pl, acc, partials, G, accumulate, nullptr, nullptr, stream);
 }

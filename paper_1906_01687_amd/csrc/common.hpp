@@ -81,6 +81,8 @@ int device_cu_count();
 // LDS bytes a gradient workgroup may use for privatised FP64 partials.
 constexpr int64_t kLdsBudgetBytes = 156 * 1024;
 constexpr int64_t kLdsLimitBytes = 160 * 1024;  // dynamic LDS of one workgroup on gfx950
+// FP32 device accumulation while a mode averages at most this many adds per element
+constexpr int64_t kAcc32MaxAdds = 1024;
 
 // Bytes of one staged sample record (row offsets of d modes, value, weight),
 // padded to 16 like the device struct.
@@ -101,12 +103,17 @@ struct ScatterPlan {
     int lds_elem;                       // bytes per LDS element: 8 (FP64) or 4 (FP32, CAS adds)
     uint32_t stage_off;                 // byte offset of the per-wave sample records, or 0xFFFFFFFF
     int64_t shm_bytes;                  // dynamic LDS of one gradient workgroup
-    int64_t acc_off[GCP_MAX_D];         // offset of mode k in the FP64 atomic accumulator
-    int64_t acc_total;
+    int64_t acc_off[GCP_MAX_D];         // offset of mode k in the atomic accumulator (elements)
+    int64_t acc_total;                  // accumulator elements
+    int acc_elem;                       // bytes per accumulator element: 8 (FP64) or 4 (FP32)
+    uint32_t acc_stride;                // accumulator elements per factor row (>= r)
+    uint32_t acc_magic;                 // ceil(2^32 / r) when acc_stride != r, else 0
     int64_t blocks;                     // gradient workgroups (= number of partials)
     int threads;                        // threads per gradient workgroup
 };
 ScatterPlan plan_scatter(const gcp_tensor* X, const gcp_factors* M, int64_t n_items);
+// 8-byte words of the atomic accumulator (what a workspace holds and a clear covers)
+inline int64_t acc_words(const ScatterPlan& pl) { return (pl.acc_total * pl.acc_elem + 7) / 8; }
 size_t scatter_partials_bytes(const ScatterPlan& pl, int fdtype);
 int64_t fused_items(const gcp_tensor* X, const gcp_sampling* cfg, int64_t ncand);
 

@@ -55,8 +55,10 @@ struct ReduceArgs {
     int64_t lds_total;
     int64_t nparts;
     const void* partials;
-    const double* acc;
+    const double* acc;  // FP32 elements when acc_elem == 4
     int64_t acc_off[GCP_MAX_D];
+    int64_t r, acc_stride;
+    int acc_elem;
     void* G[GCP_MAX_D];
     // Adam (fused variant)
     void* A;
@@ -501,9 +503,13 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(ReduceArgs a) {
     } else {
         __syncthreads();
         const int64_t local = lb * kRedThreads + threadIdx.x;
-        if (local < nk)
-            finish_element<GT, ADAM>(a, k, local, a.acc[a.acc_off[k] + local], ADAM ? bc_shared[0] : 1.0,
-                                     ADAM ? bc_shared[1] : 1.0, false, GT(0), GT(0), GT(0), 0.f);
+        if (local < nk) {
+            const int64_t e = a.acc_off[k] + (a.acc_stride == a.r ? local
+                                                                   : local / a.r * a.acc_stride + local % a.r);
+            const double g = a.acc_elem == 4 ? (double)reinterpret_cast<const float*>(a.acc)[e] : a.acc[e];
+            finish_element<GT, ADAM>(a, k, local, g, ADAM ? bc_shared[0] : 1.0, ADAM ? bc_shared[1] : 1.0, false,
+                                     GT(0), GT(0), GT(0), 0.f);
+        }
     }
 }
 
@@ -592,11 +598,34 @@ ScatterPlan plan_scatter(const gcp_tensor* X, const gcp_factors* M, int64_t n_it
     pl.lds_elem = use32 ? 4 : 8;
     const int64_t lds = use32 ? n32 : n64;
     for (int k = 0; k < X->d; ++k) pl.lds_off[k] = use32 ? offs32[k] : offs64[k];
+    // device accumulator of the other modes.  A device atomic costs about one
+    // L2 operation per 64-byte sector its row touches (measured: 10 FP32
+    // columns at a 40-byte stride take 1.6x the time of the same adds with rows
+    // padded to 64 bytes), so rows are padded to a power of two up to 64 bytes
+    // and to a multiple of 64 beyond.  FP32 and BF16 factors accumulate in FP32
+    // while a mode's rows average at most kAcc32MaxAdds adds per element (the
+    // FP32 sum then stays well inside the FP32 gradient's tolerance), else FP64.
+    const int64_t samples = n_items * kWave;
+    bool acc32 = M->dtype != GCP_F64;
+    for (int k = 0; k < X->d; ++k)
+        if (!((pl.priv_mask >> k) & 1u) && samples > kAcc32MaxAdds * X->dims[k]) acc32 = false;
+    pl.acc_elem = acc32 ? 4 : 8;
+    const int64_t row_bytes = r * pl.acc_elem;
+    int64_t pad_bytes = row_bytes <= 64 ? 4 : (row_bytes + 63) / 64 * 64;
+    while (pad_bytes < row_bytes) pad_bytes <<= 1;
+    int64_t stride = pad_bytes / pl.acc_elem;
+    // the kernel's row offsets are 32-bit
+    for (int k = 0; k < X->d; ++k)
+        if (!((pl.priv_mask >> k) & 1u) && X->dims[k] * stride > (int64_t)UINT32_MAX) stride = r;
+    pl.acc_stride = (uint32_t)stride;
+    // q = i r < 2^32 (a factor block is below 4 GiB), so umulhi(q, ceil(2^32 / r))
+    // is exactly i: the product is i 2^32 + i e with e = r ceil(2^32 / r) - 2^32 < r
+    pl.acc_magic = stride != r ? (uint32_t)(((1ull << 32) + (uint64_t)r - 1) / (uint64_t)r) : 0u;
     int64_t acc = 0;
     for (int k = 0; k < X->d; ++k)
         if (!((pl.priv_mask >> k) & 1u)) {
             pl.acc_off[k] = acc;
-            acc += X->dims[k] * r;
+            acc += X->dims[k] * stride;
         }
     pl.lds_total = lds;
     pl.acc_total = acc;
@@ -685,6 +714,9 @@ static GradArgs base_args(const gcp_tensor* X, const gcp_factors* M, const Scatt
         a.lds_off[k] = pl.lds_off[k];
         a.acc_off[k] = pl.acc_off[k];
     }
+    a.acc_stride = pl.acc_stride;
+    a.acc_magic = pl.acc_magic;
+    a.acc32 = pl.acc_elem == 4;
     a.priv_mask = pl.priv_mask;
     a.lds_total = pl.lds_total;
     a.stage_off = pl.stage_off;
@@ -772,6 +804,9 @@ gcp_status launch_reduce(const gcp_factors* M, const ScatterPlan& pl, const doub
         a.acc_off[k] = pl.acc_off[k];
         a.G[k] = G ? G[k] : nullptr;
     }
+    a.r = M->rank;
+    a.acc_stride = pl.acc_stride;
+    a.acc_elem = pl.acc_elem;
     a.priv_mask = pl.priv_mask;
     a.lds_total = pl.lds_total;
     a.nparts = pl.blocks;

@@ -39,8 +39,14 @@ struct GradArgs {
     int64_t lds_off[GCP_MAX_D];
     int64_t lds_total;
     void* partials;  // [gridDim.x][lds_total], FP64 for FP64 factors, else FP32
+    // device accumulator of the modes not privatised: FP64, or FP32 when
+    // acc32; row i of mode k starts at element acc_off[k] + i * acc_stride,
+    // and the kernel forms i * acc_stride from q = i * r as
+    // umulhi(q, acc_magic) * acc_stride when acc_magic != 0
     double* acc;
     int64_t acc_off[GCP_MAX_D];
+    uint32_t acc_stride, acc_magic;
+    int acc32;
     double w[5];
     double eps;
     double* loss_sum;
@@ -333,7 +339,9 @@ struct PhaseB {
     double kz;
     __amdgpu_buffer_rsrc_t rs[D];
     uint32_t lbase[D];
-    double* accj[D];
+    void* accj[D];
+    uint32_t acc_stride, acc_magic;
+    bool acc32;
 };
 
 template <int NB, int D, typename FT, bool LIST, typename LT, bool STAGED>
@@ -401,8 +409,14 @@ __device__ __forceinline__ void pass_batches(const GradArgs& a, const PhaseB<D, 
                         lds_add(reinterpret_cast<LT*>(reinterpret_cast<char*>(lds) + b.lbase[k] +
                                                       qq[u][k] * (uint32_t)sizeof(LT)),
                                 (LT)v);
-                    else
-                        unsafeAtomicAdd(b.accj[k] + qq[u][k], (double)v);
+                    else {
+                        uint32_t row = qq[u][k];
+                        if (b.acc_magic) row = __umulhi(row, b.acc_magic) * b.acc_stride;
+                        if (b.acc32)
+                            unsafeAtomicAdd(static_cast<float*>(b.accj[k]) + row, (float)v);
+                        else
+                            unsafeAtomicAdd(static_cast<double*>(b.accj[k]) + row, (double)v);
+                    }
                 }
             }
         }
@@ -435,7 +449,11 @@ __device__ __forceinline__ void evaluate_and_scatter(const GradArgs& a, LT* __re
     b.priv = uni(a.priv_mask);
     b.colj = (int)b.j < b.r;
     b.kz = a.kz;
-    double* const acc = uni(a.acc);
+    char* const acc = reinterpret_cast<char*>(uni(a.acc));
+    b.acc32 = uni(a.acc32) != 0;
+    b.acc_stride = uni(a.acc_stride);
+    b.acc_magic = uni(a.acc_magic);
+    const int64_t acc_elem = b.acc32 ? 4 : 8;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         const uint64_t bytes = (uint64_t)uni(a.dims.n[k]) * (uint64_t)b.r * sizeof(FT);
@@ -443,7 +461,7 @@ __device__ __forceinline__ void evaluate_and_scatter(const GradArgs& a, LT* __re
                                                     (int)(bytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)bytes),
                                                     kBufferWord3);
         b.lbase[k] = (uint32_t)((uni(a.lds_off[k]) + (int64_t)b.j) * (int64_t)sizeof(LT));
-        b.accj[k] = acc ? acc + uni(a.acc_off[k]) + b.j : nullptr;
+        b.accj[k] = acc ? acc + (uni(a.acc_off[k]) + (int64_t)b.j) * acc_elem : nullptr;
     }
     // passes per batch: as many as keep a batch's registers (indices, value,
     // weight and gathered entries) within about 64 VGPRs

@@ -151,6 +151,14 @@ CASES = [
     ("dense_bf16_r64_fp32_lds", lambda: small_dense(dims=(120, 110, 100), rank=64, s=5000, dtype="bf16")),
     # mode 0 (6000 x 8) exceeds the LDS budget even in FP32: device-atomic fallback
     ("counts_semi_long_mode", lambda: small_sparse("counts", dims=(6000, 7, 5), rank=8, p=20000, q=30000)),
+    # device accumulator rows padded to sector bounds: FP32 rows of 10 at a
+    # 16-element stride, FP32 rows of 33 at 48, FP64 rows of 5 at 8
+    ("counts_semi_long_mode_r10", lambda: small_sparse("counts", dims=(6000, 7, 5), rank=10, p=20000, q=30000)),
+    ("counts_strat_long_mode_r33", lambda: small_sparse("counts", dims=(1500, 6, 5), rank=33, p=9000, q=7000,
+                                                        sampler=synth.STRATIFIED)),
+    ("dense_f64_long_mode_r5", lambda: small_dense(dims=(5000, 9, 7), rank=5, s=20000, dtype="f64")),
+    # FP32 factors, but over 1024 adds per element of the long mode: FP64 accumulator
+    ("dense_f32_long_mode_many_adds", lambda: small_dense(dims=(700, 5, 4), rank=64, s=800000)),
 ]
 
 
