@@ -468,15 +468,20 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(ReduceArgs a) {
         }
         double s = 0.0;
         if (in) {
-            // sixteen independent partial sums keep sixteen loads in flight; they
-            // are combined in a fixed order, so the result does not depend on timing
+            // U independent partial sums keep U loads in flight; they are
+            // combined in a fixed order, so the result does not depend on timing
             const int64_t pe = a.lds_off[k] + local;
             const GT* __restrict__ parts = static_cast<const GT*>(a.partials);  // partial type = gradient type
             constexpr int U = GCP_REDUCE_UNROLL;
             double acc16[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) acc16[u] = 0.0;
-            int64_t b = wv;
+            // full batches of U loads, then at most one batch that re-reads the
+            // last partial past the end and drops those values (issued together,
+            // without a branch between the loads); the wave index is made scalar so
+            // the partial offsets are scalar arithmetic
+            const int64_t wvu = __builtin_amdgcn_readfirstlane(wv);
+            int64_t b = wvu;
             for (; b + (U - 1) * kRedWaves < a.nparts; b += U * kRedWaves) {
                 GT v[U];
 #pragma unroll
@@ -484,7 +489,17 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(ReduceArgs a) {
 #pragma unroll
                 for (int u = 0; u < U; ++u) acc16[u] += (double)v[u];
             }
-            for (; b < a.nparts; b += kRedWaves) acc16[0] += (double)parts[b * a.lds_total + pe];
+            if (b < a.nparts) {
+                const int64_t last = a.nparts - 1;
+                GT v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t bu = b + u * kRedWaves;
+                    v[u] = parts[(bu < last ? bu : last) * a.lds_total + pe];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) acc16[u] += b + u * kRedWaves < a.nparts ? (double)v[u] : 0.0;
+            }
 #pragma unroll
             for (int w = U / 2; w > 0; w >>= 1)
 #pragma unroll
