@@ -132,8 +132,10 @@ __global__ __launch_bounds__(1024) void batched_grad_kernel(BatchGradArgs ba) {
             // the next item's gathers are in flight while this one is evaluated
             Sample<D, T> nxt = item + nwib < un.item_end ? draw(item + nwib) : no_sample<D, T>();
             to_rows(a, cur);
-            if (f32) evaluate_and_scatter<D, FT, false, float>(a, reinterpret_cast<float*>(lds), stage, cur, fsum);
-            else evaluate_and_scatter<D, FT, false, double>(a, lds, stage, cur, fsum);
+            if (f32)
+                evaluate_and_scatter<D, FT, false, float, false>(a, reinterpret_cast<float*>(lds), stage, cur, fsum);
+            else
+                evaluate_and_scatter<D, FT, false, double, false>(a, lds, stage, cur, fsum);
             cur = nxt;
         }
         const int32_t next = u + 1 < u_end ? ba.units[u + 1].problem : -1;

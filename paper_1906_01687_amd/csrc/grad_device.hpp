@@ -433,7 +433,9 @@ __device__ __forceinline__ void pass_batches(const GradArgs& a, const PhaseB<D, 
 // one pass covers 64/lps samples.  Passes are taken 2 to 8 at a time so that
 // the row gathers of a batch are all in flight before any of them is
 // consumed.  Every lane of the wave must call this.
-template <int D, typename FT, bool LIST, typename LT = double>
+// PADDED_ACC = false fixes the device accumulator to FP64 rows of r (the
+// batched kernel's layout), so none of the padded-row code is generated.
+template <int D, typename FT, bool LIST, typename LT = double, bool PADDED_ACC = true>
 __device__ __forceinline__ void evaluate_and_scatter(const GradArgs& a, LT* __restrict__ lds,
                                                      Sample<D, typename Compute<FT>::type>* stage,
                                                      const Sample<D, typename Compute<FT>::type>& smp,
@@ -450,9 +452,15 @@ __device__ __forceinline__ void evaluate_and_scatter(const GradArgs& a, LT* __re
     b.colj = (int)b.j < b.r;
     b.kz = a.kz;
     char* const acc = reinterpret_cast<char*>(uni(a.acc));
-    b.acc32 = uni(a.acc32) != 0;
-    b.acc_stride = uni(a.acc_stride);
-    b.acc_magic = uni(a.acc_magic);
+    if constexpr (PADDED_ACC) {
+        b.acc32 = uni(a.acc32) != 0;
+        b.acc_stride = uni(a.acc_stride);
+        b.acc_magic = uni(a.acc_magic);
+    } else {
+        b.acc32 = false;
+        b.acc_stride = 0;
+        b.acc_magic = 0;
+    }
     const int64_t acc_elem = b.acc32 ? 4 : 8;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
