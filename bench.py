@@ -78,11 +78,29 @@ KERNEL_SOURCES = ["paper_1906_01687_amd/csrc/grad.hip", "paper_1906_01687_amd/cs
                   "paper_1906_01687_amd/csrc/device.hpp", "paper_1906_01687_amd/csrc/common.hpp"]
 
 
+def kernel_source_hash(read=None) -> str:
+    """SHA-256 of the gradient kernel's sources with comments and whitespace
+    removed, so that a comment edit does not retire a profile but any code
+    change does.  ``read(rel)`` returns a source's text (default: the tree)."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        if read is None:
+            with open(os.path.join(ROOT, rel), encoding="utf-8") as fh:
+                text = fh.read()
+        else:
+            text = read(rel)
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update("".join(text.split()).encode())
+    return h.hexdigest()
+
+
 def profiled_traffic(workload: str):
     """HBM bytes per launch of the gradient kernel from the committed PMC summary
     (FETCH_SIZE + WRITE_SIZE, calibrated on a copy), or None when there is no
     summary for this workload or the kernel sources changed since it was taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"grad_kernel_{workload}.md")
     if not os.path.exists(path):
         return None
@@ -93,11 +111,8 @@ def profiled_traffic(workload: str):
             fields[k.strip()] = v.strip()
     if "traffic_bytes_per_launch" not in fields or "kernel_source_sha256" not in fields:
         return None
-    h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            h.update(fh.read())
-    if h.hexdigest() != fields["kernel_source_sha256"]:
+    h = kernel_source_hash()
+    if h != fields["kernel_source_sha256"]:
         return None
     return int(fields["traffic_bytes_per_launch"])
 

@@ -17,11 +17,13 @@
 //
 // Scatter.  Device-scope atomics on MI355X sustain only ~170 G element-adds/s
 // (measured), far below what plain stores reach, so every mode whose rows fit
-// is accumulated privately per workgroup in LDS (FP64 ds_add), and each
-// workgroup writes its dense partial once with ordinary stores (rounded to
-// FP32).  A reduction kernel then sums the partials in FP64 in a fixed order
-// (deterministic).  Modes too long for LDS fall back to FP64 device atomics
-// into an accumulator that the call clears first.
+// is accumulated privately per workgroup in LDS (FP64 ds_add, or FP32 by
+// compare-and-swap), and each workgroup writes its dense partial once with
+// ordinary stores (rounded to FP32 for FP32/BF16 factors).  A reduction kernel
+// then sums the partials in FP64 in a fixed order (deterministic).  Modes too
+// long for LDS fall back to device atomics into an accumulator that the call
+// clears first: rows padded to 64-byte sectors, FP32 for FP32/BF16 factors
+// unless a row averages many adds, else FP64.
 //
 // Stratified zeros.  The count kernel (sample.hip) has counted the accepted
 // candidates of every 64-candidate chunk and a scan has turned the counts
@@ -367,7 +369,7 @@ __global__ __launch_bounds__(256) void loss_grad_kernel(LossArgs a) {
 
 // ---------------------------------------------------------------------------
 // Reduction: G = the sum of the per-workgroup partials (fixed order, FP64)
-// for privatised modes and the FP64 accumulator for the others, optionally
+// for privatised modes and the device accumulator for the others, optionally
 // followed by the Adam step on the same elements.  Elements are numbered over
 // all modes in mode order (the flat parameter layout).  A privatised mode
 // gets workgroups of 64 elements whose 16 waves each sum every 16th partial
