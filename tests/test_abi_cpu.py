@@ -307,3 +307,19 @@ def test_factor_match_score():
     est = [np.stack([0.6 * e[0] + 0.5 * e[1] + np.sqrt(1 - 0.61) * e[2],
                      0.5 * e[0] + 0.1 * e[1] + np.sqrt(1 - 0.26) * e[2]], axis=1)]
     assert abs(factor_match_score(ref, est) - 0.5) < 1e-12
+
+
+def test_profile_hash_ignores_comments_only():
+    """bench.py keeps a committed traffic figure across comment edits of the
+    gradient kernel sources and retires it on any code change."""
+    import bench
+    base = {rel: open(os.path.join(bench.ROOT, rel), encoding="utf-8").read() for rel in bench.KERNEL_SOURCES}
+    h0 = bench.kernel_source_hash(lambda rel: base[rel])
+    assert h0 == bench.kernel_source_hash()
+    first = bench.KERNEL_SOURCES[0]
+    commented = dict(base)
+    commented[first] = "// a new comment\n/* and a block\n   comment */\n" + base[first].replace("\n", "\n  ", 3)
+    assert bench.kernel_source_hash(lambda rel: commented[rel]) == h0
+    changed = dict(base)
+    changed[first] = base[first] + "\nstatic int gcp_unused_probe = 1;\n"
+    assert bench.kernel_source_hash(lambda rel: changed[rel]) != h0
