@@ -156,7 +156,9 @@ static gcp_status check_sampling(const gcp_tensor* X, const gcp_sampling* cfg) {
     if (!cfg) return set_error(GCP_ERR_INVALID_ARG, "cfg is NULL");
     switch (cfg->sampler) {
     case GCP_SAMPLER_FULL:
-        if (X->format == GCP_COO && X->nnz > 0) {
+        // every entry's value is looked up in the nonzero table, also when
+        // the tensor stores no entries
+        if (X->format == GCP_COO && full_count(X) > 0) {
             if (gcp_status st = check_table(X)) return st;
         }
         break;

@@ -83,6 +83,14 @@ def test_argument_errors_are_reported_without_launching():
     cfg.p, cfg.q = 10, 10
     st = L.gcp_sample(ctypes.byref(t), ctypes.byref(cfg), 0x10, 0x10, 0x10, None, 0, None)
     assert st == 1 and b"COO" in L.gcp_last_error()
+    # FULL on a COO tensor looks every entry up in the nonzero table, so the
+    # table is required even when the tensor stores no entries
+    t.format = m.COO
+    t.nnz = 0
+    cfg.sampler = m.FULL
+    st = L.gcp_sample(ctypes.byref(t), ctypes.byref(cfg), 0x10, 0x10, 0x10, None, 0, None)
+    assert st == 1 and b"nz_table" in L.gcp_last_error()
+    t.format = m.DENSE
     t.d = 9
     cfg.sampler = m.UNIFORM
     cfg.s = 5
