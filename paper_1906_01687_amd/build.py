@@ -17,6 +17,8 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libgcp.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 SOURCES = ["abi.cpp", "sample.hip", "grad.hip", "adam.hip", "batched.hip"]
+# the kernels of each mode count d = 1..8 are instantiated in their own object
+MODE_COUNTS = range(1, 9)
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -29,9 +31,11 @@ FLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(job) -> str:
+    src, defines = job if isinstance(job, tuple) else (job, {})
+    stem = os.path.splitext(src)[0] + "".join(f"_{k.lower()}{v}" for k, v in defines.items())
+    obj = os.path.join(BUILD_DIR, stem + ".o")
+    cmd = [HIPCC, *FLAGS, *[f"-D{k}={v}" for k, v in defines.items()], "-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -42,8 +46,9 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
-    with concurrent.futures.ThreadPoolExecutor(max_workers=min(4, os.cpu_count() or 1)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+    jobs = [("inst.hip", {"GCP_INST_D": d}) for d in MODE_COUNTS] + list(SOURCES)
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        objs = list(ex.map(_compile, jobs))
     tmp = OUT + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
