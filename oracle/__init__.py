@@ -40,11 +40,16 @@ def build(force: bool = True) -> str:
 
 
 def lib():
+    """The loaded oracle; GCP_ORACLE_LIB names another build of gcp_oracle.c
+    (the sanitizer test loads an instrumented one)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
-            build(force=True)
-        L = ctypes.CDLL(_LIB_PATH)
+        path = os.environ.get("GCP_ORACLE_LIB")
+        if not path:
+            path = _LIB_PATH
+            if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+                build(force=True)
+        L = ctypes.CDLL(path)
         u64, i64, i32, dbl = ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         P = ctypes.c_void_p
         L.orc_philox4x64_10.argtypes = [P, P, P]
@@ -80,8 +85,14 @@ def _ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
+_mutation = 0
+
+
 def set_mutation(m: int) -> None:
-    """Plant deliberate mistake ``m`` (0 = none); used only by the pin tests."""
+    """Plant deliberate mistake ``m`` (0 = none); used only by the pin tests.
+    Mistakes 1-8 live in the C code, 9 in adam_fit below."""
+    global _mutation
+    _mutation = int(m)
     lib().orc_set_mutation(int(m))
 
 
@@ -291,7 +302,9 @@ def adam_fit(loss: int, dims, A0, *, dense=None, coo_idx=None, coo_val=None, gra
         epoch += 1
         history.append(F)
         if F > F_old:
-            A[:], B[:], C[:], t = saved[0], saved[1], saved[2], saved[3]
+            A[:], B[:], C[:] = saved[0], saved[1], saved[2]
+            if _mutation != 9:                       # 9 planted: the step count is not wound back
+                t = saved[3]
             F = F_old
             alpha *= nu
             bad += 1

@@ -356,7 +356,9 @@ double orc_grad_weighted(int loss, int d, const int64_t *dims, int64_t r, const 
             f = w * (we * orc_loss_f(loss, x, m, eps) - wz * orc_loss_f(loss, 0.0, m, eps));
         } else {
             y = w * we * orc_loss_g(loss, x, m, eps);
-            f = w * we * orc_loss_f(loss, x, m, eps);
+            /* 8 planted: a zero sample's loss term weighted omega/q instead of zeta/q */
+            double wf = (g_mutation == 8 && st == ORC_S_ZERO) ? omega / (double)q : w;
+            f = wf * we * orc_loss_f(loss, x, m, eps);
         }
         if (ytilde_out) ytilde_out[c] = y;
         F += f;

@@ -81,6 +81,17 @@ def exact_gradient(loss, X, A, eps=oracle.LOSS_EPS, W=None):
     return G
 
 
+def exact_loss(loss, X, A, eps=oracle.LOSS_EPS, W=None):
+    """F(X, M) = sum_i f(x_i, m_i) over every entry (eq. gcp); with entry
+    weights W, sum_i w_i f(x_i, m_i) (eq. wgcp)."""
+    M = full_model(A)
+    fvec = np.vectorize(lambda x, m: oracle.loss_f(loss, float(x), float(m), eps))
+    Fm = fvec(X, M)
+    if W is not None:
+        Fm = Fm * W
+    return float(Fm.sum())
+
+
 def enumeration_samples(dims, X):
     """Every index once, uniform stratum, in row-major order (s = number of entries)."""
     grids = np.meshgrid(*[np.arange(n) for n in dims], indexing="ij")
@@ -637,6 +648,113 @@ def pin_adam_fit_undo():
     return ok, f"unchanged {same}, accepted {acc}, alpha {alpha}"
 
 
+def pin_loss_estimate_unbiased(sampler, weighted=False, N=4000):
+    """The oracle's loss estimate -- eq. Fhat (uniform), eq. Fhat-strat
+    (stratified), and for semi-stratified sampling the correction reading
+    sum_nz (eta/p)[f(x, m) - f(0, m)] + sum_zero (omega/q) f(0, m) -- has
+    mean F(X, M) = sum_i f(x_i, m_i) over every entry (eq. gcp), or the
+    weighted sum_i w_i f(x_i, m_i) (eq. wgcp): the mean of N estimates lies
+    within 3 standard errors of the enumerated value."""
+    loss = {oracle.UNIFORM: oracle.GAUSSIAN, oracle.STRATIFIED: oracle.BERNOULLI_ODDS,
+            oracle.SEMI_STRATIFIED: oracle.POISSON}[sampler]
+    W = None
+    if sampler == oracle.UNIFORM:
+        X, A = tiny_dense((4, 3, 5), r=2)
+        data, nnz = dict(dense=X), 0
+        if weighted:
+            W = np.random.default_rng(62).uniform(0.0, 2.0, size=X.shape)
+            wkw = dict(dense_w=W)
+    elif weighted:
+        loss = oracle.POISSON if sampler == oracle.SEMI_STRATIFIED else oracle.BERNOULLI_ODDS
+        X, coo, val, A, coo_w, w_zero, W = _weighted_case()
+        data, nnz = dict(coo_idx=coo, coo_val=val), coo.shape[0]
+        wkw = dict(coo_idx=coo, coo_w=coo_w, w_zero=w_zero)
+    else:
+        X, coo, val, A = tiny_sparse("binary" if loss == oracle.BERNOULLI_ODDS else "counts")
+        data, nnz = dict(coo_idx=coo, coo_val=val), coo.shape[0]
+    dims = X.shape
+    F_exact = exact_loss(loss, X, A, W=W)
+    s, p, q = 30, 20, 25
+    est = np.empty(N)
+    for t in range(N):
+        smp = oracle.sample(sampler, dims, s=s, p=p, q=q, seed=53, iteration=t, **data)
+        kw = dict(nnz=nnz, s=s, p=p, q=q)
+        if weighted:
+            kw.update(wgt=oracle.entry_weights(dims, smp, **wkw), w_zero=wkw.get("w_zero", 1.0))
+        est[t] = oracle.grad(loss, dims, A, smp, **kw)[1]
+    se = float(est.std(ddof=1)) / math.sqrt(N)
+    dev = abs(float(est.mean()) - F_exact)
+    return dev <= 3.0 * se, f"|mean - F| = {dev:.4g}, 3 s.e. = {3.0 * se:.4g} (F = {F_exact:.6g})"
+
+
+def _fit_by_alg4(loss, dims, A0, X, gcfg, ecfg, alpha, nu, tau, kappa, max_epochs, beta1=0.9, beta2=0.999,
+                 eps=1e-8):
+    """Alg. 4 written out independently of oracle.adam_fit: after an epoch whose
+    estimate rose, A, B, C and the step count t go back to their values at the
+    start of the epoch (t <- t - tau) and the rate is scaled by nu."""
+    d = len(dims)
+    r = A0[0].shape[1]
+    A = [np.array(a, dtype=np.float64) for a in A0]
+    B = [np.zeros_like(a) for a in A]
+    C = [np.zeros_like(a) for a in A]
+    est_smp = oracle.sample(ecfg["sampler"], dims, dense=X, s=ecfg["s"], seed=ecfg["seed"])
+    F = oracle.grad(loss, dims, A, est_smp, s=ecfg["s"])[1]
+    t, draws, bad, accepted = 0, 0, 0, [True]
+    for _ in range(max_epochs):
+        if bad > kappa:
+            break
+        A_keep, B_keep, C_keep = [a.copy() for a in A], [b.copy() for b in B], [c.copy() for c in C]
+        for _ in range(tau):
+            smp = oracle.sample(gcfg["sampler"], dims, dense=X, s=gcfg["s"], seed=gcfg["seed"], iteration=draws)
+            draws += 1
+            G, _ = oracle.grad(loss, dims, A, smp, s=gcfg["s"])
+            t += 1
+            flatA = np.concatenate([a.reshape(-1) for a in A])
+            flatB = np.concatenate([b.reshape(-1) for b in B])
+            flatC = np.concatenate([c.reshape(-1) for c in C])
+            oracle.adam(flatA, np.concatenate([g.reshape(-1) for g in G]), flatB, flatC, t, alpha=alpha,
+                        beta1=beta1, beta2=beta2, eps=eps)
+            off = 0
+            for k in range(d):
+                n = dims[k] * r
+                A[k] = flatA[off:off + n].reshape(dims[k], r)
+                B[k] = flatB[off:off + n].reshape(dims[k], r)
+                C[k] = flatC[off:off + n].reshape(dims[k], r)
+                off += n
+        F_new = oracle.grad(loss, dims, A, est_smp, s=ecfg["s"])[1]
+        if F_new > F:
+            A, B, C = A_keep, B_keep, C_keep
+            t -= tau
+            alpha *= nu
+            bad += 1
+            accepted.append(False)
+        else:
+            F = F_new
+            accepted.append(True)
+    return A, accepted
+
+
+def pin_adam_fit_rewind():
+    """Alg. 4's undo winds the step count back (t <- t - tau), so the bias
+    corrections of the epoch after an undone one are those of a fresh epoch:
+    with a rate that overshoots in the first epoch only, oracle.adam_fit
+    (undo, then kept epochs) equals the loop written out here bit for bit."""
+    dims, r = (6, 5, 4), 2
+    rng = np.random.default_rng(43)
+    A_true = [rng.standard_normal((n, r)) for n in dims]
+    X = full_model(A_true) + 0.05 * rng.standard_normal(dims)
+    A0 = [rng.standard_normal((n, r)) for n in dims]
+    gcfg = dict(sampler=oracle.UNIFORM, s=40, seed=7)
+    ecfg = dict(sampler=oracle.UNIFORM, s=500, seed=8)
+    A, _, acc, _ = oracle.adam_fit(oracle.GAUSSIAN, dims, A0, dense=X, grad_cfg=gcfg, est_cfg=ecfg, alpha=3.0,
+                                   nu=0.1, tau=10, kappa=2, max_epochs=4)
+    A_ref, acc_ref = _fit_by_alg4(oracle.GAUSSIAN, dims, A0, X, gcfg, ecfg, alpha=3.0, nu=0.1, tau=10, kappa=2,
+                                  max_epochs=4)
+    pattern = acc_ref[:3] == [True, False, True]
+    same = acc == acc_ref and all(np.array_equal(a, b) for a, b in zip(A, A_ref))
+    return pattern and same, f"accepted {acc} (written-out loop {acc_ref}), factors equal {same}"
+
+
 ALL_PINS = {
     "philox_numpy": pin_philox_numpy,
     "randi_exact": pin_randi_exact,
@@ -668,4 +786,11 @@ ALL_PINS = {
     "cp_score": pin_cp_score,
     "adam_fit_recovers": pin_adam_fit_recovers,
     "adam_fit_undo": pin_adam_fit_undo,
+    "adam_fit_rewind": pin_adam_fit_rewind,
+    "loss_estimate_uniform": lambda: pin_loss_estimate_unbiased(oracle.UNIFORM),
+    "loss_estimate_stratified": lambda: pin_loss_estimate_unbiased(oracle.STRATIFIED),
+    "loss_estimate_semi": lambda: pin_loss_estimate_unbiased(oracle.SEMI_STRATIFIED),
+    "loss_estimate_weighted_uniform": lambda: pin_loss_estimate_unbiased(oracle.UNIFORM, weighted=True),
+    "loss_estimate_weighted_stratified": lambda: pin_loss_estimate_unbiased(oracle.STRATIFIED, weighted=True),
+    "loss_estimate_weighted_semi": lambda: pin_loss_estimate_unbiased(oracle.SEMI_STRATIFIED, weighted=True),
 }

@@ -5,7 +5,10 @@ Mutations (planted inside the oracle only, switched by a test hook):
 3 semi-stratified "zero" weight zeta/q instead of omega/q; 4 semi-stratified
 nonzero correction -g(0,m) dropped; 5 the wrong factor left out of the
 Khatri-Rao row; 6 Adam epsilon moved outside the square root; 7 weighted
-semi-stratified correction uses the entry's own weight instead of w_zero.
+semi-stratified correction uses the entry's own weight instead of w_zero;
+8 the loss estimate weights a stratified zero by omega/q instead of zeta/q
+(the gradient keeps the right weight); 9 GCP-Adam's undo leaves the step
+count where the undone epoch ended.
 """
 import pytest
 
@@ -20,6 +23,8 @@ EXPECTED = {
     5: {"enumeration_equals_unfolding", "gaussian_closed_form", "poisson_closed_form"},
     6: {"adam_closed_forms"},
     7: {"weighted_unbiased_semi"},
+    8: {"loss_estimate_stratified", "loss_estimate_weighted_stratified"},
+    9: {"adam_fit_rewind"},
 }
 
 
