@@ -206,7 +206,13 @@ gcp_status gcp_nz_bitmap_build(const gcp_tensor *X, uint32_t *bitmap, size_t byt
  * tensor looks values up through X->nz_table.  ws: gcp_sample_workspace_bytes
  * bytes (0 except for STRATIFIED).  The rejection loop is exact: if the first
  * candidate batch holds fewer than q zeros, a device-side loop continues the
- * counter stream until q are found (no host round trip). */
+ * counter stream until q are found (no host round trip).  That loop examines
+ * at most 2^22 further candidates; a configuration whose first batch
+ * (cfg->rho times q omega / zeta) plus that cap falls short of q omega / zeta
+ * plus eight standard deviations of the candidate count (App. B) is refused
+ * with GCP_ERR_UNSUPPORTED, so the cap is reached with probability below
+ * 1e-15.  If it is reached, the rejection status word reads 1 (see
+ * gcp_rejection_status_offset) and the unfilled zero slots hold no samples. */
 size_t gcp_sample_workspace_bytes(const gcp_tensor *X, const gcp_sampling *cfg);
 gcp_status gcp_sample(const gcp_tensor *X, const gcp_sampling *cfg,
                       uint32_t *idx, void *xval, uint8_t *stratum,
@@ -251,6 +257,15 @@ gcp_status gcp_mttkrp(const gcp_tensor *X, const gcp_factors *M, const uint32_t 
  * gcp_sample with the same cfg; G equal to gcp_sample -> gcp_loss_grad ->
  * gcp_mttkrp up to floating-point summation order.  G and loss_sum as in
  * gcp_mttkrp and gcp_loss_grad (G is overwritten). */
+/* Byte offset, in the workspace of a STRATIFIED call with q > 0, of the
+ * rejection status word (uint32): 0 once the call has drawn all q zeros, 1 if
+ * the device refill stopped at its cap (Sec. 4.2, Alg. 2; see gcp_sample).
+ * M == NULL: the workspace of gcp_sample; otherwise that of gcp_sampled_grad
+ * and gcp_sampled_adam_step with these factors.  -1 when the call has no
+ * rejection step.  The word is written on the call's stream; read it after
+ * the call completes. */
+int64_t gcp_rejection_status_offset(const gcp_tensor *X, const gcp_factors *M, const gcp_sampling *cfg);
+
 size_t gcp_sampled_grad_workspace_bytes(const gcp_tensor *X, const gcp_factors *M,
                                         const gcp_sampling *cfg);
 gcp_status gcp_sampled_grad(gcp_loss loss, const gcp_tensor *X, const gcp_factors *M,

@@ -233,8 +233,22 @@ def _ptr_array(tensors) -> ctypes.Array:
 # entry points
 # ---------------------------------------------------------------------------
 
-def sample(X: DataTensor, cfg: GcpSampling, stream=None):
-    """gcp_sample: (idx [S, d] int32, xval [S], stratum [S] uint8)."""
+def _rejection_status(X: DataTensor, M: Optional["Factors"], cfg: GcpSampling, ws: torch.Tensor) -> int:
+    """The rejection status word of a finished call (0: all q zeros drawn; 1:
+    the device refill stopped at its cap); 0 for calls without rejection."""
+    t = X.struct()
+    m = M.struct() if M is not None else None
+    off = int(lib().gcp_rejection_status_offset(ctypes.byref(t), ctypes.byref(m) if m is not None else None,
+                                                ctypes.byref(cfg)))
+    if off < 0:
+        return 0
+    return int(ws[off:off + 4].cpu().view(torch.int32)[0].item())
+
+
+def sample(X: DataTensor, cfg: GcpSampling, stream=None, check_status: bool = False):
+    """gcp_sample: (idx [S, d] int32, xval [S], stratum [S] uint8).  With
+    check_status, waits for the call and raises if the rejection refill
+    stopped at its cap."""
     L = lib()
     dev = X.values.device
     S = n_samples(cfg, X)
@@ -246,6 +260,8 @@ def sample(X: DataTensor, cfg: GcpSampling, stream=None):
     ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
     check(L.gcp_sample(ctypes.byref(t), ctypes.byref(cfg), _ptr(idx), _ptr(xval), _ptr(st),
                        _ptr(ws), nbytes, _stream(stream)))
+    if check_status and _rejection_status(X, None, cfg, ws) != 0:
+        raise _lib.GcpError(2, "stratified rejection stopped at its refill cap")
     return idx[:S], xval[:S], st[:S]
 
 
@@ -306,6 +322,10 @@ class SampledGrad:
                                      _ptr(self.ws), self.nbytes, _stream(stream)))
         return self.out
 
+    def rejection_status(self) -> int:
+        """Status word of the last call's rejection step (waits for it)."""
+        return _rejection_status(self.X, self.M, self.cfg, self.ws)
+
 
 def sampled_grad(loss, X: DataTensor, M: Factors, cfg: GcpSampling, eps: float = LOSS_EPS,
                  out=None, with_loss: bool = False, stream=None):
@@ -342,6 +362,10 @@ class SampledAdamStep:
             _ptr(M.flat), _ptr(M.master), _ptr(a.B), _ptr(a.C), _ptr(a.state), float(a.lr), float(a.beta1),
             float(a.beta2), float(a.eps), float(a.lower), int(a.eps_mode), self.out_ptrs, _ptr(self.loss_sum),
             _ptr(self.ws), self.nbytes, _stream(stream)))
+
+    def rejection_status(self) -> int:
+        """Status word of the last call's rejection step (waits for it)."""
+        return _rejection_status(self.X, self.M, self.cfg, self.ws)
 
 
 class Adam:

@@ -182,6 +182,19 @@ static gcp_status check_sampling(const gcp_tensor* X, const gcp_sampling* cfg) {
             if (!(zeta > 0.0)) return set_error(GCP_ERR_INVALID_ARG, "stratified zeros requested but X has no zeros");
             if (zeta < omega * (1.0 / 1048576.0))
                 return set_error(GCP_ERR_UNSUPPORTED, "rejection needs zeros to be at least 2^-20 of the entries");
+            // Drawing q zeros takes a negative-binomial number of candidates:
+            // mean q / pi, standard deviation sqrt(q (1 - pi)) / pi, for the
+            // zero fraction pi = zeta / omega (Sec. 4.2, App. B).  The first
+            // batch (rho times the mean) and the device refill cap must cover
+            // the mean plus eight standard deviations.
+            const double pi = zeta / omega, q = (double)cfg->q;
+            const double need = q / pi + 8.0 * std::sqrt(q * (1.0 - pi)) / pi;
+            const double have = (double)rejection_batch(X, cfg) + (double)kRejRefillCandidates;
+            if (need > have)
+                return set_error(GCP_ERR_UNSUPPORTED,
+                                 "stratified rejection: q zeros need about " + std::to_string((int64_t)need) +
+                                     " candidates, beyond the first batch plus the refill cap (" +
+                                     std::to_string((int64_t)have) + "); raise cfg->rho");
         }
         break;
     }
@@ -483,6 +496,22 @@ gcp_status gcp_mttkrp(const gcp_tensor* X, const gcp_factors* M, const uint32_t*
     if (gcp_status st = launch_fill_zero(acc, acc_words(pl), stream)) return st;
     if (gcp_status st = launch_grad_list(X, M, idx, ytilde, S, pl, acc, partials, stream)) return st;
     return launch_reduce(M, pl, acc, partials, G, accumulate, nullptr, nullptr, stream);
+}
+
+int64_t gcp_rejection_status_offset(const gcp_tensor* X, const gcp_factors* M, const gcp_sampling* cfg) {
+    if (!X || !cfg || X->d < 1 || X->d > GCP_MAX_D) return -1;
+    if (cfg->sampler != GCP_SAMPLER_STRATIFIED || cfg->q <= 0) return -1;
+    char* const base = reinterpret_cast<char*>(size_t(1) << 40);  // carve against a fake base, keep offsets
+    if (!M) {
+        Carver c;
+        RejScratch rs{};
+        sample_ws(X, cfg, c, base, &rs);
+        return rs.status ? (int64_t)(reinterpret_cast<char*>(rs.status) - base) : -1;
+    }
+    if (M->rank < 1) return -1;
+    FusedLayout f{};
+    fused_ws(X, M, cfg, base, &f);
+    return f.rs.status ? (int64_t)(reinterpret_cast<char*>(f.rs.status) - base) : -1;
 }
 
 size_t gcp_sampled_grad_workspace_bytes(const gcp_tensor* X, const gcp_factors* M, const gcp_sampling* cfg) {

@@ -53,8 +53,14 @@ struct Carver {
 // 64 (one wave), chunk counts are scanned, then ranked per chunk.
 constexpr int kRejChunk = 64;
 constexpr int kRejThreads = 256;
-// Refill loop cap (tiles of 1024 candidates beyond the first batch).
-constexpr int64_t kRejMaxRefillTiles = int64_t(1) << 22;
+// Refill loop cap: one wave examines at most this many turns of 64
+// candidates beyond the first batch (about 4.2e6 candidates, tens of ms).
+// The host refuses a configuration whose first batch plus this cap falls short
+// of the expected candidate count q omega / zeta by eight standard deviations,
+// so the cap is reached with probability below 1e-15; if it is reached, the
+// status word of the rejection scratch reads 1.
+constexpr int64_t kRejRefillTurns = int64_t(1) << 16;
+constexpr int64_t kRejRefillCandidates = kRejRefillTurns * 64;
 
 // Number of candidates in the first rejection batch.
 int64_t rejection_batch(const gcp_tensor* X, const gcp_sampling* cfg);
@@ -65,7 +71,7 @@ struct RejScratch {
     uint64_t* chunk_prefix;  // [nchunks + 1]: exclusive prefixes, then the total (scan)
     uint32_t* group_sum;     // [ngroups]: accepted per 4 chunks (fused path; else NULL)
     uint32_t* zstage;        // [nchunks * 64 * d]: accepted indices per chunk (fused path; else NULL)
-    uint32_t* status;        // [1] 0 ok, 1 refill cap reached
+    uint32_t* status;        // [1] 0 ok, 1 refill cap reached (cleared by the count kernel)
     int64_t nchunks;
     int64_t ngroups;
 };

@@ -473,6 +473,7 @@ gcp_status launch_grad_fused(gcp_loss loss, const gcp_tensor* X, const gcp_facto
             a.ngroups = rs->ngroups;
             a.chunk_prefix = scanned ? rs->chunk_prefix : nullptr;
             a.n_zero_items = rs->nchunks;
+            a.rej_status = rs->status;
         }
     }
     a.n_direct_items = (a.n_direct + kWave - 1) / kWave;

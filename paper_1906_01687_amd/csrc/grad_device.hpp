@@ -30,6 +30,7 @@ struct GradArgs {
     const uint32_t* group_sum;
     const uint32_t* zstage;
     const uint64_t* chunk_prefix;  // non-NULL when a scan provided the prefixes
+    uint32_t* rej_status;          // set to 1 if the refill stops at its cap
     // list mode (gcp_mttkrp): indices and ytilde per sample
     const uint32_t* idx;
     const void* ytilde;
@@ -148,8 +149,16 @@ template <int D, typename T>
 struct alignas(16) Sample {
     uint32_t q[D];  // i_k from phase A; i_k * r after to_rows()
     T x;            // data value (list mode: ytilde)
-    T w;            // stratum weight, negated for a corrected nonzero (g(x,m) - g(0,m)); 0: no sample
+    T w;            // stratum weight; sign bit set for a corrected nonzero (g(x,m) - g(0,m)); +0: no sample
 };
+
+// The sign bit of a sample's weight marks a corrected nonzero (Sec. 4.3), and
+// only +0 marks an empty slot: a corrected nonzero whose entry weight is 0
+// (eq. wgcp) has w = -0 and still carries its -kz g(0, m) term.
+__device__ __forceinline__ bool corrected(float w) { return (__float_as_uint(w) >> 31) != 0u; }
+__device__ __forceinline__ bool corrected(double w) { return __double_as_longlong(w) < 0; }
+__device__ __forceinline__ bool carries(float w) { return __float_as_uint(w) != 0u; }
+__device__ __forceinline__ bool carries(double w) { return __double_as_longlong(w) != 0; }
 
 template <int D, typename T>
 __device__ __forceinline__ Sample<D, T> no_sample() {
@@ -252,12 +261,13 @@ __device__ __forceinline__ double rroot(double y) { return 1.0 / sqrt(y); }
 __device__ __forceinline__ float rroot(float y) { return __builtin_amdgcn_rsqf(y); }
 
 // w * g(x, m) for the loss's derivative g (Sec. 1, 4.2 and 5.3).  A corrected
-// nonzero of semi-stratified sampling (Sec. 4.3, Alg. 3) carries w < 0 and
-// gives |w| g(x, m) - kz g(0, m), with kz = (eta/p) w_zero; unweighted, |w| =
-// kz and this is |w| (g(x, m) - g(0, m)), only the part of g that depends on x.
+// nonzero of semi-stratified sampling (Sec. 4.3, Alg. 3) carries the sign bit
+// and gives |w| g(x, m) - kz g(0, m), with kz = (eta/p) w_zero; unweighted,
+// |w| = kz and this is |w| (g(x, m) - g(0, m)), only the part of g that
+// depends on x.
 template <typename T>
 __device__ __forceinline__ T weighted_g(int loss, T x, T m, T w, T eps, T kz) {
-    const bool corr = w < T(0);
+    const bool corr = corrected(w);
     const T aw = corr ? -w : w;
     // g = base(m) - t(x, m): the x-free part and the part linear in x
     T base, t;
@@ -287,7 +297,7 @@ __device__ __forceinline__ T weighted_g(int loss, T x, T m, T w, T eps, T kz) {
 // |w| (f(x, m) - f(0, m)) when unweighted.
 template <typename T>
 __device__ __forceinline__ T weighted_f(int loss, T x, T m, T w, T eps, T kz) {
-    if (w >= T(0)) return w * loss_f<T>(loss, x, m, eps);
+    if (!corrected(w)) return w * loss_f<T>(loss, x, m, eps);
     const T aw = -w;
     const T f0 = loss_f<T>(loss, T(0), m, eps);
     return aw * (loss_f<T>(loss, x, m, eps) - f0) + (aw - kz) * f0;
@@ -392,7 +402,7 @@ __device__ __forceinline__ void pass_batches(const GradArgs& a, const PhaseB<D, 
             suf[D - 1] = T(1);
 #pragma unroll
             for (int k = D - 2; k >= 0; --k) suf[k] = suf[k + 1] * av[u][k + 1];
-            const bool live = ww[u] != T(0);
+            const bool live = carries(ww[u]);
             T y;
             if constexpr (LIST) {
                 y = xx[u];

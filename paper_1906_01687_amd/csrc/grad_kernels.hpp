@@ -117,7 +117,7 @@ __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
                 // zeros: continue the counter stream (wave-uniform loop)
                 uint64_t filled = batch_total(a);
                 uint64_t base = (uint64_t)a.ncand;
-                for (int64_t t = 0; t < kRejMaxRefillTiles * 16 && filled < (uint64_t)a.q; ++t) {
+                for (int64_t t = 0; t < kRejRefillTurns && filled < (uint64_t)a.q; ++t) {
                     const uint64_t jj = base + lane;
                     uint32_t i[D];
                     const bool ok = candidate_accepted<D>(a.dims, a.tab, a.seed, a.pid, iter, jj, i);
@@ -130,6 +130,7 @@ __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
                     filled += __popcll(b2);
                     base += kWave;
                 }
+                if (lane == 0 && filled < (uint64_t)a.q) a.rej_status[0] = 1;
             }
         }
         cur = nxt;

@@ -157,6 +157,7 @@ __global__ __launch_bounds__(kRejThreads) void rej_count_kernel(RejArgs a) {
     const uint64_t bal = __ballot(acc);
     const int64_t chunk = j / kRejChunk;
     const uint32_t cnt = (uint32_t)__popcll(bal);
+    if (j == 0) a.status[0] = 0;
     if (a.zstage && acc) {
         const int64_t o = chunk * kRejChunk + __popcll(bal & ((1ull << lane) - 1ull));
 #pragma unroll
@@ -202,7 +203,6 @@ __global__ __launch_bounds__(1024) void rej_scan_kernel(RejArgs a) {
     }
     if (tid == 0) {
         a.chunk_prefix[a.nchunks] = carry;
-        a.status[0] = 0;
     }
 }
 
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(kWave) void rej_refill_kernel(RejArgs a) {
     if (filled >= (uint64_t)a.q) return;
     const uint64_t iter = effective_iteration(a.iter, a.iter_ctr);
     uint64_t base = (uint64_t)a.ncand;
-    for (int64_t t = 0; t < kRejMaxRefillTiles * 16 && filled < (uint64_t)a.q; ++t) {
+    for (int64_t t = 0; t < kRejRefillTurns && filled < (uint64_t)a.q; ++t) {
         uint32_t i[D];
         const bool acc = candidate_accepted<D>(a.dims, a.tab, a.seed, a.pid, iter, base + lane, i);
         const uint64_t bal = __ballot(acc);

@@ -331,3 +331,40 @@ def test_profile_hash_ignores_comments_only():
     changed = dict(base)
     changed[first] = base[first] + "\nstatic int gcp_unused_probe = 1;\n"
     assert bench.kernel_source_hash(lambda rel: changed[rel]) != h0
+
+
+def test_rejection_cap_refused_on_the_host():
+    """Stratified rejection whose first batch plus the device refill cap
+    (2^22 candidates) cannot cover q omega / zeta plus eight standard
+    deviations of the candidate count (Sec. 4.2, App. B) is refused before any
+    launch; a larger rho makes the same request acceptable."""
+    m = _lib()
+    L = m.lib()
+    t = m.GcpTensor()
+    t.d, t.format, t.vdtype = 2, m.COO, m.F32
+    t.dims[0], t.dims[1] = 1 << 20, 1 << 10      # omega = 2^30
+    t.nnz = (1 << 30) - (1 << 12)                 # zeta = 2^12 = 2^-18 omega
+    t.coo_idx, t.values = 0x1000, 0x1000
+    t.nz_bitmap = 0x1000
+    cfg = m.GcpSampling()
+    cfg.sampler = m.STRATIFIED
+    cfg.p, cfg.q = 0, 1000
+    cfg.rho = 0.5                                 # first batch: half the mean of 2.6e8 candidates
+    st = L.gcp_sample(ctypes.byref(t), ctypes.byref(cfg), 0x10, 0x10, 0x10, None, 0, None)
+    assert st == 2 and b"refill cap" in L.gcp_last_error()
+    # expected candidates q omega / zeta = 2.6e8, standard deviation 8.3e6:
+    # rho = 1.3 covers the mean plus eight deviations
+    cfg.rho = 1.3
+    assert L.gcp_sample_workspace_bytes(ctypes.byref(t), ctypes.byref(cfg)) > 0
+    # the host check passes; only the missing workspace is reported
+    st = L.gcp_sample(ctypes.byref(t), ctypes.byref(cfg), 0x10, 0x10, 0x10, None, 0, None)
+    assert st == 4 and b"workspace" in L.gcp_last_error(), L.gcp_last_error()
+    # the status word lies inside the workspace, for the materialising and the fused call
+    off = L.gcp_rejection_status_offset(ctypes.byref(t), None, ctypes.byref(cfg))
+    assert 0 <= off < L.gcp_sample_workspace_bytes(ctypes.byref(t), ctypes.byref(cfg))
+    M = m.GcpFactors()
+    M.dtype, M.rank = m.F32, 4
+    offf = L.gcp_rejection_status_offset(ctypes.byref(t), ctypes.byref(M), ctypes.byref(cfg))
+    assert 0 <= offf < L.gcp_sampled_grad_workspace_bytes(ctypes.byref(t), ctypes.byref(M), ctypes.byref(cfg))
+    cfg.sampler = m.SEMI_STRATIFIED
+    assert L.gcp_rejection_status_offset(ctypes.byref(t), None, ctypes.byref(cfg)) == -1

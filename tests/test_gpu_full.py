@@ -11,7 +11,7 @@ import oracle
 import synth
 import paper_1906_01687_amd as gcp
 from paper_1906_01687_amd import variance
-from gpu_cases import TORCH_DT, host_rounded, rel_fro, small_dense, small_sparse
+from gpu_cases import TORCH_DT, check_grad, grad_scale, host_rounded, rel_fro, small_dense, small_sparse
 
 pytestmark = pytest.mark.gpu
 
@@ -54,10 +54,13 @@ def test_full_gradient_is_the_enumeration(name, make, dtype, bitmap):
     idx, xv, st = gcp.sample(X, cfg)
     torch.cuda.synchronize()
     tol = 1e-12 if dtype == "f64" else 1e-5
-    assert max(rel_fro(G, Gref)) <= tol
+    omega = int(np.prod(w.dims))
+    ref_idx = np.stack(np.unravel_index(np.arange(omega), w.dims), axis=1)
+    enum = oracle.Samples(ref_idx, dense.reshape(-1), np.zeros(omega, np.int32), np.arange(omega), omega)
+    E = grad_scale(w.loss, w.dims, host_rounded(w.A_init, dtype), enum, s=omega)
+    check_grad(G, Gref, E, tol, f"FULL {name}")
     assert abs(fs.item() - Fref) <= 10 * tol * max(1.0, abs(Fref))
     # the materialised enumeration: entry c in row-major order, its value, weight-1 stratum
-    ref_idx = np.stack(np.unravel_index(np.arange(int(np.prod(w.dims))), w.dims), axis=1)
     assert np.array_equal(idx.cpu().numpy().astype(np.int64), ref_idx)
     assert np.array_equal(xv.cpu().to(torch.float64).numpy(), dense.reshape(-1))
     assert int(st.max()) == 0
