@@ -250,13 +250,6 @@ gcp_status gcp_mttkrp(const gcp_tensor *X, const gcp_factors *M, const uint32_t 
                       const void *ytilde, int64_t S, void *const *G, int accumulate,
                       void *ws, size_t ws_bytes, hipStream_t stream);
 
-/* ---------------------------------------------------------------------------
- * gcp_sampled_grad -- the whole stochastic gradient of Alg. 1 / 2 / 3 in as
- * few launches as possible: draws, model entries, derivatives and the MTTKRP
- * of every mode, without writing the samples out.  Same samples as
- * gcp_sample with the same cfg; G equal to gcp_sample -> gcp_loss_grad ->
- * gcp_mttkrp up to floating-point summation order.  G and loss_sum as in
- * gcp_mttkrp and gcp_loss_grad (G is overwritten). */
 /* Byte offset, in the workspace of a STRATIFIED call with q > 0, of the
  * rejection status word (uint32): 0 once the call has drawn all q zeros, 1 if
  * the device refill stopped at its cap (Sec. 4.2, Alg. 2; see gcp_sample).
@@ -266,6 +259,13 @@ gcp_status gcp_mttkrp(const gcp_tensor *X, const gcp_factors *M, const uint32_t 
  * the call completes. */
 int64_t gcp_rejection_status_offset(const gcp_tensor *X, const gcp_factors *M, const gcp_sampling *cfg);
 
+/* ---------------------------------------------------------------------------
+ * gcp_sampled_grad -- the whole stochastic gradient of Alg. 1 / 2 / 3 in as
+ * few launches as possible: draws, model entries, derivatives and the MTTKRP
+ * of every mode, without writing the samples out.  Same samples as
+ * gcp_sample with the same cfg; G equal to gcp_sample -> gcp_loss_grad ->
+ * gcp_mttkrp up to floating-point summation order.  G and loss_sum as in
+ * gcp_mttkrp and gcp_loss_grad (G is overwritten). */
 size_t gcp_sampled_grad_workspace_bytes(const gcp_tensor *X, const gcp_factors *M,
                                         const gcp_sampling *cfg);
 gcp_status gcp_sampled_grad(gcp_loss loss, const gcp_tensor *X, const gcp_factors *M,
