@@ -272,6 +272,22 @@ gcp_status gcp_sampled_grad(gcp_loss loss, const gcp_tensor *X, const gcp_factor
                             const gcp_sampling *cfg, double eps, void *const *G,
                             double *loss_sum, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* gcp_sampled_grad_noalloc -- gcp_sampled_grad for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same kernels, with the workspace taken
+ * from a static device array of GCP_NOALLOC_SCRATCH_BYTES that the library
+ * holds on every device it runs on until the process ends.  The caller still
+ * passes X, M, G and loss_sum.  The call allocates nothing; the first call on
+ * a device looks the array up there (hipGetSymbolAddress).  A problem whose
+ * gcp_sampled_grad_workspace_bytes exceeds the array is refused with
+ * GCP_ERR_WORKSPACE before any launch.  Every call on a device shares that
+ * device's array, and each call clears what must start at zero: calls that
+ * overlap on one device (two streams) race, so serialise them. */
+#define GCP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+gcp_status gcp_sampled_grad_noalloc(gcp_loss loss, const gcp_tensor *X, const gcp_factors *M,
+                                    const gcp_sampling *cfg, double eps, void *const *G,
+                                    double *loss_sum, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
  * gcp_sampled_adam_step -- one iteration of Alg. 4's inner loop: the
  * stochastic gradient of gcp_sampled_grad followed by the Adam step of

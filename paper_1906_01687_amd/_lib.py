@@ -78,7 +78,7 @@ EXPORTS = [
     "gcp_last_error", "gcp_abi_version", "gcp_nz_table_slots", "gcp_nz_table_bytes",
     "gcp_nz_index_build", "gcp_nz_bitmap_bytes", "gcp_nz_bitmap_build", "gcp_sample_workspace_bytes", "gcp_sample", "gcp_loss_grad",
     "gcp_mttkrp_workspace_bytes", "gcp_mttkrp", "gcp_rejection_status_offset", "gcp_sampled_grad_workspace_bytes",
-    "gcp_sampled_grad", "gcp_sampled_adam_step", "gcp_adam_step", "gcp_timing_start",
+    "gcp_sampled_grad", "gcp_sampled_grad_noalloc", "gcp_sampled_adam_step", "gcp_adam_step", "gcp_timing_start",
     "gcp_timing_stop", "gcp_batched_create", "gcp_batched_workspace_bytes", "gcp_batched_prepare", "gcp_batched_plan", "gcp_adam_fit_workspace_bytes", "gcp_adam_fit",
     "gcp_batched_grad", "gcp_batched_adam_step", "gcp_batched_destroy",
 ]
@@ -113,6 +113,7 @@ def lib() -> ctypes.CDLL:
         "gcp_rejection_status_offset": (i64, [T, M, S]),
         "gcp_sampled_grad_workspace_bytes": (sz, [T, M, S]),
         "gcp_sampled_grad": (st, [ctypes.c_int, T, M, S, dbl, P, P, P, sz, P]),
+        "gcp_sampled_grad_noalloc": (st, [ctypes.c_int, T, M, S, dbl, P, P, P]),
         "gcp_sampled_adam_step": (st, [ctypes.c_int, T, M, S, dbl, P, P, P, P, P, dbl, dbl, dbl, dbl, dbl,
                                        ctypes.c_int, P, P, P, sz, P]),
         "gcp_adam_step": (st, [i64, ctypes.c_int, P, P, P, P, P, P, dbl, dbl, dbl, dbl, dbl,

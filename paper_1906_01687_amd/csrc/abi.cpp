@@ -1,6 +1,7 @@
 // abi.cpp -- the extern "C" entry points of libgcp: host-side argument
 // validation, workspace sizing and carving, and the launch sequence of each
 // call.  No device synchronisation and no allocation happen here.
+#include <hip/hip_runtime.h>
 #include <hip/hip_runtime_api.h>
 
 #include <math.h>
@@ -341,6 +342,35 @@ static gcp_status sampled_common(gcp_loss loss, const gcp_tensor* X, const gcp_f
     return launch_reduce(M, f.plan, f.acc, f.partials, G, 0, adam, cfg->iteration_counter, stream);
 }
 
+// Workspace of gcp_sampled_grad_noalloc: one array per device, shared by
+// every call on that device.  Host code never uses the array's name as an
+// address (in host code it is only a stand-in for the symbol): the device
+// address comes from hipGetSymbolAddress, once per device, with that device
+// current.
+static __device__ __align__(256) unsigned char scratch[GCP_NOALLOC_SCRATCH_BYTES];
+
+static gcp_status scratch_address(void** out) {
+    static std::mutex mu;
+    static void* addr[64] = {nullptr};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        (void)hipGetLastError();
+        return set_error(GCP_ERR_HIP, "gcp_sampled_grad_noalloc: no current HIP device (or more than 64)");
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return set_error(GCP_ERR_HIP, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+        }
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return GCP_OK;
+}
+
 // One problem of a batch (gcp_batched_create).
 static gcp_status check_problem(const gcp_problem* pr, int32_t b) {
     const std::string at = "problem " + std::to_string(b) + ": ";
@@ -531,6 +561,28 @@ gcp_status gcp_sampled_grad(gcp_loss loss, const gcp_tensor* X, const gcp_factor
     for (int k = 0; k < X->d; ++k)
         if (!G[k]) return set_error(GCP_ERR_INVALID_ARG, "G[" + std::to_string(k) + "] is NULL");
     return sampled_common(loss, X, M, cfg, eps, G, loss_sum, ws, ws_bytes, nullptr, stream);
+}
+
+gcp_status gcp_sampled_grad_noalloc(gcp_loss loss, const gcp_tensor* X, const gcp_factors* M,
+                                    const gcp_sampling* cfg, double eps, void* const* G, double* loss_sum,
+                                    hipStream_t stream) {
+    clear_error();
+    if (gcp_status st = check_loss(loss)) return st;
+    if (gcp_status st = check_tensor(X)) return st;
+    if (gcp_status st = check_sampling(X, cfg)) return st;
+    if (gcp_status st = check_factors(X, M)) return st;
+    if (!G) return set_error(GCP_ERR_INVALID_ARG, "G is NULL");
+    for (int k = 0; k < X->d; ++k)
+        if (!G[k]) return set_error(GCP_ERR_INVALID_ARG, "G[" + std::to_string(k) + "] is NULL");
+    const size_t need = fused_ws(X, M, cfg, nullptr, nullptr);
+    if (need > GCP_NOALLOC_SCRATCH_BYTES)
+        return set_error(GCP_ERR_WORKSPACE, "gcp_sampled_grad_noalloc: the call needs " + std::to_string(need) +
+                                                " bytes of scratch, above the static " +
+                                                std::to_string((size_t)GCP_NOALLOC_SCRATCH_BYTES) +
+                                                "; use gcp_sampled_grad with a workspace");
+    void* ws = nullptr;
+    if (gcp_status st = scratch_address(&ws)) return st;
+    return sampled_common(loss, X, M, cfg, eps, G, loss_sum, ws, GCP_NOALLOC_SCRATCH_BYTES, nullptr, stream);
 }
 
 gcp_status gcp_sampled_adam_step(gcp_loss loss, const gcp_tensor* X, const gcp_factors* M, const gcp_sampling* cfg,

@@ -368,3 +368,23 @@ def test_rejection_cap_refused_on_the_host():
     assert 0 <= offf < L.gcp_sampled_grad_workspace_bytes(ctypes.byref(t), ctypes.byref(M), ctypes.byref(cfg))
     cfg.sampler = m.SEMI_STRATIFIED
     assert L.gcp_rejection_status_offset(ctypes.byref(t), None, ctypes.byref(cfg)) == -1
+
+
+def test_noalloc_refuses_problems_beyond_its_scratch():
+    """gcp_sampled_grad_noalloc refuses, before any launch, a problem whose
+    workspace exceeds its static scratch (64 MiB)."""
+    m = _lib()
+    L = m.lib()
+    t = _dense_struct(m, (400000, 200, 30))      # mode 0 takes a 102 MB device accumulator
+    M = m.GcpFactors()
+    M.dtype, M.rank = m.F32, 64
+    for k in range(3):
+        M.A[k] = 0x1000
+    cfg = m.GcpSampling()
+    cfg.sampler = m.UNIFORM
+    cfg.s = 50_000_000
+    need = L.gcp_sampled_grad_workspace_bytes(ctypes.byref(t), ctypes.byref(M), ctypes.byref(cfg))
+    assert need > (64 << 20)
+    G = (ctypes.c_void_p * 3)(0x1000, 0x1000, 0x1000)
+    st = L.gcp_sampled_grad_noalloc(0, ctypes.byref(t), ctypes.byref(M), ctypes.byref(cfg), 1e-10, G, None, None)
+    assert st == 4 and b"static" in L.gcp_last_error(), L.gcp_last_error()
