@@ -1,17 +1,26 @@
 """Benchmark: sampled GCP gradient + Adam step on one MI355X.
 
 A step is one pass of the whole hot path over one fresh sample set: index
-draws (stratified: nonzero picks plus zeros by rejection), model entries,
-weighted loss derivatives, the MTTKRP scatter into every mode, and the Adam
-update -- the library's gcp_sampled_adam_step, with all inputs resident in
-HBM.  The default workload is the sparse binary tensor
-1000x800x600 (about 1e6 nonzeros, rank 8, FP32 factors, Bernoulli-odds loss,
-stratified sampling p = q = 1e5).
+draws, data lookups, model entries, weighted loss derivatives, the MTTKRP
+scatter into every mode, and the Adam update, with all inputs resident in HBM.
+
+Default workload: 64 independent dense 3-way problems in one persistent
+launch pair (gcp_batched_adam_step) -- cubes with sides log-uniform in
+[20, 300], ranks in {4, 8, 16, 32}, Gaussian / Poisson / Bernoulli-odds
+losses, 2 % of each cube's entries sampled per step (3.34e6 samples).  The
+same 64 problems are also timed as 64 single-problem fused steps (the plain
+launch).  `--workload` selects a single-problem workload instead: the sparse
+binary 1000x800x600 tensor (stratified sampling), the count tensor
+6000x24x77x32 (semi-stratified), the dense 30x40x50 and 200^4 Gaussian
+tensors (uniform).
 
 Prints one JSON line.  `value` is sampled entries per second over the timed
-steps; `roofline` prices the dominant kernel (the fused gradient kernel) by
-its algorithmic bytes against MI355X's 8 TB/s; `cpu_baseline` times the FP64
-oracle on a bounded sample of the same workload on one host core.
+steps; `roofline` prices the dominant kernel by its algorithmic bytes against
+MI355X's 8 TB/s, with the HBM traffic rocprofv3 measured for it; `issue`
+gives the same kernel's VALU and LDS instruction rates against the chip's
+issue peaks (from the committed counter summary); `cpu_baseline` times the
+FP64 oracle on a bounded sample of the same workload on the host's cores
+(one process per core), with the one-thread rate beside it.
 """
 from __future__ import annotations
 
@@ -36,12 +45,18 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="sparse_binary_1000x800x600",
-                    help="sparse_binary_1000x800x600 | sparse_count_6000x24x77x32 | dense_gaussian_30x40x50 | "
-                         "dense_gaussian_200x200x200x200[_bf16] | batched_64_cubes")
+    ap.add_argument("--workload", default="batched_64_cubes",
+                    help="batched_64_cubes | sparse_binary_1000x800x600 | sparse_count_6000x24x77x32 | "
+                         "dense_gaussian_30x40x50 | dense_gaussian_200x200x200x200[_bf16]")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="bound on the oracle timing")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="oracle processes for the CPU baseline (0: the usable cores, at most 16)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch every step eagerly")
+    ap.add_argument("--launch-shape", default="",
+                    help="batched workload: threads,unit_items,schedule,cols_per_lane instead of autotuning")
+    ap.add_argument("--cols-per-lane", type=int, default=0,
+                    help="rank columns per lane of the gradient kernels (1, 2, 4; 0 = by rank)")
     ap.add_argument("--autograd", action="store_true",
                     help="also time the step as SampledLoss forward + backward + Adam")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -74,18 +89,29 @@ def algorithmic_bytes(w) -> float:
     return w.p * (per + 4 * d + bv) + w.q * (per + zero_data)
 
 
-KERNEL_SOURCES = ["paper_1906_01687_amd/csrc/grad.hip", "paper_1906_01687_amd/csrc/grad_device.hpp",
-                  "paper_1906_01687_amd/csrc/device.hpp", "paper_1906_01687_amd/csrc/common.hpp"]
+_CSRC = "paper_1906_01687_amd/csrc/"
+# sources whose code decides what the single-problem gradient kernel executes
+KERNEL_SOURCES = [_CSRC + f for f in ("grad_kernels.hpp", "grad_device.hpp", "device.hpp", "kernels.hpp",
+                                      "common.hpp", "grad.hip")]
+# the same for the batched gradient kernel
+BATCH_KERNEL_SOURCES = [_CSRC + f for f in ("batched_kernels.hpp", "batched.hip", "grad_device.hpp", "device.hpp",
+                                            "kernels.hpp", "common.hpp")]
+
+# MI355X issue peaks (256 CUs at 2.4 GHz): a wave64 VALU instruction occupies
+# one of a CU's four 16-lane SIMDs for 4 cycles; the LDS takes one instruction
+# per CU per cycle.  In G wave-instructions per second.
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4 / 1e9
+LDS_ISSUE_PEAK = 256 * 2.4e9 / 1e9
 
 
-def kernel_source_hash(read=None) -> str:
-    """SHA-256 of the gradient kernel's sources with comments and whitespace
-    removed, so that a comment edit does not retire a profile but any code
-    change does.  ``read(rel)`` returns a source's text (default: the tree)."""
+def kernel_source_hash(read=None, sources=None) -> str:
+    """SHA-256 of a kernel's sources with comments and whitespace removed, so
+    that a comment edit does not retire a profile but any code change does.
+    ``read(rel)`` returns a source's text (default: the tree)."""
     import hashlib
     import re
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in (sources or KERNEL_SOURCES):
         if read is None:
             with open(os.path.join(ROOT, rel), encoding="utf-8") as fh:
                 text = fh.read()
@@ -97,11 +123,11 @@ def kernel_source_hash(read=None) -> str:
     return h.hexdigest()
 
 
-def profiled_traffic(workload: str):
-    """HBM bytes per launch of the gradient kernel from the committed PMC summary
-    (FETCH_SIZE + WRITE_SIZE, calibrated on a copy), or None when there is no
-    summary for this workload or the kernel sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", f"grad_kernel_{workload}.md")
+def profiled(name: str, sources):
+    """The ``key: value`` figures of profiles/<name>.md (HBM bytes and
+    instruction counts per launch from rocprofv3 PMC passes), or None when
+    there is no summary or the kernel's sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{name}.md")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -109,58 +135,130 @@ def profiled_traffic(workload: str):
         if ":" in line and not line.startswith(("|", "#", " ", "`")):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
-    if "traffic_bytes_per_launch" not in fields or "kernel_source_sha256" not in fields:
+    if fields.get("kernel_source_sha256") != kernel_source_hash(sources=sources):
         return None
-    h = kernel_source_hash()
-    if h != fields["kernel_source_sha256"]:
-        return None
-    return int(fields["traffic_bytes_per_launch"])
+    return fields
 
 
-def cpu_baseline(w, seconds: float):
+def issue_rates(fields, kernel_us: float):
+    """VALU and LDS wave-instruction rates of a kernel (counts per launch from
+    its profile over the live kernel duration) against the issue peaks."""
+    if not fields or "sq_insts_valu_per_launch" not in fields:
+        return None
+    valu = float(fields["sq_insts_valu_per_launch"]) / (kernel_us * 1e-6) / 1e9
+    lds = float(fields["sq_insts_lds_per_launch"]) / (kernel_us * 1e-6) / 1e9
+    return {"unit": "G wave-instructions/s",
+            "valu": {"achieved": valu, "peak": VALU_ISSUE_PEAK, "frac": valu / VALU_ISSUE_PEAK},
+            "lds": {"achieved": lds, "peak": LDS_ISSUE_PEAK, "frac": lds / LDS_ISSUE_PEAK},
+            "source": "SQ_INSTS_VALU, SQ_INSTS_LDS per launch (rocprofv3 --pmc, profiles/)"}
+
+
+def usable_cores(limit: int = 16) -> int:
+    """Host cores this process may run on, capped at the GPU machine's share."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, limit))
+
+
+def copy_calibration(mib: int, dev) -> None:
+    """One device-to-device copy of `mib` MiB: the known byte count against
+    which a profiler's FETCH_SIZE and WRITE_SIZE are calibrated."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+# Workloads the oracle workers read; set before the worker processes are forked
+# (copy-on-write, nothing is pickled) and before this process touches the GPU.
+_CPU_WORKLOADS: list = []
+
+
+def _oracle_gradient(w, iteration: int) -> int:
+    """One full sampled gradient of workload w by the FP64 oracle (sample +
+    grad), on the factor values the device stores; returns its sample count."""
     import oracle
-    samples, t0, iters = 0, time.perf_counter(), 0
     kw = dict(s=w.s, p=w.p, q=w.q)
-    huge = w.dense is not None and w.dense.size > 100_000_000
+    if w.dense is not None and w.sampler == 0:
+        # uniform draws need no data; x is read from the same FP32 array the
+        # device holds (an FP64 copy of a large cube per gradient would
+        # dominate the timing)
+        smp = oracle.sample(w.sampler, w.dims, coo_idx=np.zeros((0, w.d), dtype=np.int64), coo_val=np.zeros(0),
+                            seed=w.seed, problem_id=getattr(w, "problem_id", 0), iteration=iteration, **kw)
+        smp.xval = np.asarray(w.dense)[tuple(smp.idx.T)].astype(np.float64)
+    elif w.dense is not None:
+        smp = oracle.sample(w.sampler, w.dims, dense=w.dense, seed=w.seed, iteration=iteration, **kw)
+    else:
+        smp = oracle.sample(w.sampler, w.dims, coo_idx=w.coo_idx.astype(np.int64), coo_val=w.coo_val,
+                            seed=w.seed, iteration=iteration, **kw)
+    if w.dtype == "bf16":
+        import torch
+        A64 = [torch.as_tensor(a).to(torch.float32).to(torch.bfloat16).to(torch.float64).numpy() for a in w.A_init]
+    elif w.dtype == "f32":
+        A64 = [np.float32(a).astype(np.float64) for a in w.A_init]
+    else:
+        A64 = w.A_init
+    oracle.grad(w.loss, w.dims, A64, smp, nnz=w.nnz, **kw)
+    return len(smp)
+
+
+def _oracle_worker(task):
+    """Worker `wi` of `nw`: full oracle gradients for `seconds`; with several
+    workloads it walks them in turn from its own offset, every gradient on a
+    fresh iteration of the sample stream."""
+    wi, nw, seconds = task
+    ws = _CPU_WORKLOADS
+    t0, n, k = time.perf_counter(), 0, 0
     while True:
-        if huge:
-            # the oracle's uniform draws need no data; x is read from the same
-            # FP32 array (an FP64 copy of a 6.4 GB tensor per gradient would
-            # dominate the timing)
-            smp = oracle.sample(w.sampler, w.dims, coo_idx=np.zeros((0, w.d), dtype=np.int64),
-                                coo_val=np.zeros(0), seed=w.seed, iteration=iters, **kw)
-            smp.xval = w.dense[tuple(smp.idx.T)].astype(np.float64)
-        elif w.dense is not None:
-            smp = oracle.sample(w.sampler, w.dims, dense=w.dense, seed=w.seed, iteration=iters, **kw)
-        else:
-            smp = oracle.sample(w.sampler, w.dims, coo_idx=w.coo_idx.astype(np.int64), coo_val=w.coo_val,
-                                seed=w.seed, iteration=iters, **kw)
-        A64 = [np.float32(a).astype(np.float64) for a in w.A_init] if w.dtype == "f32" else w.A_init
-        if w.dtype == "bf16":
-            import torch
-            A64 = [torch.as_tensor(a).to(torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
-                   for a in w.A_init]
-        oracle.grad(w.loss, w.dims, A64, smp, nnz=w.nnz, **kw)
-        samples += len(smp)
-        iters += 1
+        j = wi + k * nw
+        w = ws[j % len(ws)]
+        n += _oracle_gradient(w, j // len(ws))
+        k += 1
         el = time.perf_counter() - t0
-        if el >= seconds or iters >= 50:
-            break
-    return {"value": samples / el, "unit": "entries/s", "cores": 1, "kind": "oracle",
-            "sample": f"{iters} full gradients of {w.name} (oracle sample + grad, FP64, 1 thread), "
-                      f"{samples} entries in {el:.1f} s"}
+        if el >= seconds:
+            return n, el, k
 
 
-def run_batched(args):
+def cpu_baseline(workloads, name: str, seconds: float, workers: int = 0):
+    """The FP64 oracle on the host: one process per usable core (fork, before
+    the GPU is touched), each computing whole gradients of the workload(s) for
+    about `seconds`, plus the same on one thread.  entries/s = samples over
+    the slowest worker's wall time."""
+    import multiprocessing as mp
+    global _CPU_WORKLOADS
+    _CPU_WORKLOADS = list(workloads)
+    nw = workers if workers > 0 else usable_cores()
+    per_worker = max(1.5, seconds / nw)
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(processes=nw) as pool:
+        res = pool.map(_oracle_worker, [(i, nw, per_worker) for i in range(nw)])
+    wall = time.perf_counter() - t0
+    samples = sum(r[0] for r in res)
+    grads = sum(r[2] for r in res)
+    slowest = max(r[1] for r in res)
+    one = _oracle_worker((0, 1, min(seconds, 6.0)))
+    return {"value": samples / slowest, "unit": "entries/s", "cores": nw, "kind": "oracle",
+            "single_thread_value": one[0] / one[1],
+            "sample": f"{grads} full gradients of {name} (oracle sample + grad, FP64) by {nw} processes, "
+                      f"{samples} entries in {slowest:.1f} s per process ({wall:.1f} s wall); one thread: "
+                      f"{one[2]} gradients, {one[0]} entries in {one[1]:.1f} s"}
+
+
+def run_batched(args, ws, cpu):
     """64 dense cubes (sides 20..300, ranks 4..32, mixed losses, s = 2%): one
     batched step (gradient + reduction/Adam) per step, against 64 single-problem
     gcp_sampled_adam_step calls; both replayed as HIP graphs."""
     import torch
-    import synth
     import paper_1906_01687_amd as gcp
     from paper_1906_01687_amd import _lib, autotune
 
-    ws = synth.batch_of_cubes(64)
     dev = torch.device("cuda:0")
 
     def problems():
@@ -173,21 +271,24 @@ def run_batched(args):
         return out
 
     probs = problems()
-    tune, times = autotune.tune_batch(probs, cache_path=os.path.join("/tmp", "gcp_batch_tuning.json"), verbose=True)
-    print(f"[bench] autotuned launch shape (threads, unit items, schedule) = {tune}", file=sys.stderr, flush=True)
+    if args.launch_shape:
+        tune = tuple(int(v) for v in args.launch_shape.split(","))
+        print(f"[bench] launch shape (threads, unit items, schedule, cols per lane) = {tune}", file=sys.stderr,
+              flush=True)
+    else:
+        tune, times = autotune.tune_batch(probs, cache_path=os.path.join("/tmp", "gcp_batch_tuning.json"))
+        print(f"[bench] autotuned launch shape (threads, unit items, schedule, cols per lane) = {tune} "
+              f"of {len(times)} candidates", file=sys.stderr, flush=True)
     batch = gcp.Batch(probs, tune=tune, with_grad=False)
     samples = sum(w.s for w in ws)
     for _ in range(args.warmup):
         batch.adam_step(lr=0.01)
-    torch.cuda.synchronize()
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        for _ in range(args.steps):
-            batch.adam_step(lr=0.01)
+    # the K timed steps as one graph the library owns (gcp_batched_graph_capture)
+    batch.capture_adam_steps(args.steps, lr=0.01)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record()
-    graph.replay()
+    batch.graph_launch()
     stop.record()
     torch.cuda.synchronize()
     total_ms = start.elapsed_time(stop)
@@ -224,28 +325,43 @@ def run_batched(args):
     torch.cuda.synchronize()
     plain_ms = start.elapsed_time(stop) / plain_steps
 
+    if args.copy_mib > 0:
+        copy_calibration(args.copy_mib, dev)
+
     ms_per_step = total_ms / args.steps
-    bpp = {"f32": 4}
+    # algorithmic bytes per sample of a dense FP32 problem (d = 3): three
+    # factor rows (4 r each), three gradient rows read and written (8 r each),
+    # and the 4-byte data value
     balg = sum(w.s * (3 * w.rank * 4 + 3 * w.rank * 8 + 4) for w in ws)
     achieved = balg / (kernel_ms / 1e3) / 1e9
+    prof = profiled("batched_grad_kernel_batched_64_cubes", BATCH_KERNEL_SOURCES)
+    traffic = int(prof["traffic_bytes_per_launch"]) if prof and "traffic_bytes_per_launch" in prof else None
     print(f"[bench] batched: step {ms_per_step * 1e3:.1f} us (gradient kernel {kernel_ms * 1e3:.1f} us); "
           f"64 single-problem steps: {plain_ms * 1e3:.1f} us", file=sys.stderr, flush=True)
     out = {
-        "metric": "sampled gradient entries/sec & HBM GB/s (% peak)",
+        "metric": "sampled gradient entries/sec & HBM GB/s (% peak); batched vs plain at 1e-5 rel",
         "value": samples * args.steps / (total_ms / 1e3),
         "unit": "entries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batched_64_cubes", "problems": 64, "samples_per_step": samples,
                    "sides": [w.dims[0] for w in ws], "ranks": [w.rank for w in ws],
-                   "launch_shape": list(tune), "parallelism": "single_gpu"},
+                   "losses": [["gaussian", "bernoulli_odds", "poisson"][w.loss] for w in ws],
+                   "launch_shape": {"threads": tune[0], "unit_items": tune[1], "schedule": tune[2],
+                                    "cols_per_lane": tune[3] if len(tune) > 3 else 0},
+                   "parallelism": "single_gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "batched_grad_kernel", "kernel_us": kernel_ms * 1e3,
-                     "algorithmic_bytes_per_launch": balg},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "kernel": "batched_grad_kernel (64 problems: draws + model + derivative + MTTKRP scatter)",
+                     "kernel_us": kernel_ms * 1e3, "algorithmic_bytes_per_launch": balg},
+        "issue": issue_rates(prof, kernel_ms * 1e3),
+        "batched_launch": "2 kernels per step (gradient, reduction + Adam); K steps replayed as one "
+                          "library-owned HIP graph (gcp_batched_graph_capture / _launch)",
         "plain_per_problem": {"ms_per_step": plain_ms, "value": samples / (plain_ms / 1e3),
-                              "speedup_of_batched": plain_ms / ms_per_step},
-        "cpu_baseline": None,
+                              "speedup_of_batched": plain_ms / ms_per_step,
+                              "launch": "64 gcp_sampled_adam_step calls per step, one HIP graph"},
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
@@ -260,15 +376,30 @@ def main():
 
     if args.study == "variance":
         return run_variance_study(args)
+
+    # host-side inputs and the oracle baseline first: the oracle's worker
+    # processes are forked before this process touches the GPU
+    import synth
     if args.workload == "batched_64_cubes":
-        return run_batched(args)
+        ws = synth.batch_of_cubes(64)
+        cpu = None if args.no_cpu_baseline else cpu_baseline(ws, "the 64-cube batch", args.cpu_seconds,
+                                                             args.cpu_workers)
+        if cpu:
+            print(f"[bench] oracle: {cpu['value']:.3g} entries/s on {cpu['cores']} processes, "
+                  f"{cpu['single_thread_value']:.3g} on one", file=sys.stderr, flush=True)
+        if args.cols_per_lane:
+            import paper_1906_01687_amd as gcp
+            gcp.set_cols_per_lane(args.cols_per_lane)
+        return run_batched(args, ws, cpu)
+    w = synth.WORKLOADS[args.workload]()
+    cpu = None if args.no_cpu_baseline else cpu_baseline([w], w.name, args.cpu_seconds, args.cpu_workers)
 
     import torch
-    import synth
     import paper_1906_01687_amd as gcp
     from paper_1906_01687_amd import _lib
 
-    w = synth.WORKLOADS[args.workload]()
+    if args.cols_per_lane:
+        gcp.set_cols_per_lane(args.cols_per_lane)
     dev = torch.device("cuda:0")
     vdt = torch.float64 if w.dtype == "f64" else torch.float32
     tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[w.dtype]
@@ -334,26 +465,17 @@ def main():
           flush=True)
 
     if args.copy_mib > 0:
-        n = args.copy_mib * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_calibration(args.copy_mib, dev)
 
     autograd = None
     if args.autograd:
         autograd = time_autograd(args, w, X, M, sampler_name, ms_per_step)
 
-    traffic = profiled_traffic(w.name)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, args.cpu_seconds)
+    prof = profiled(f"grad_kernel_{w.name}", KERNEL_SOURCES)
+    traffic = int(prof["traffic_bytes_per_launch"]) if prof and "traffic_bytes_per_launch" in prof else None
 
     out = {
-        "metric": "sampled gradient entries/sec & HBM GB/s (% peak)",
+        "metric": "sampled gradient entries/sec & HBM GB/s (% peak); batched vs plain at 1e-5 rel",
         "value": value,
         "unit": "entries/s",
         "n_gpus": 1,
@@ -373,6 +495,7 @@ def main():
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "grad_kernel (fused draws + model + derivative + MTTKRP scatter)",
                      "kernel_us": kernel_ms * 1e3, "algorithmic_bytes_per_launch": balg},
+        "issue": issue_rates(prof, kernel_ms * 1e3),
         "cpu_baseline": cpu,
     }
     if autograd is not None:

@@ -48,7 +48,7 @@ extern "C" {
 
 #define GCP_ABI_VERSION 1
 #define GCP_MAX_D 8        /* modes per tensor */
-#define GCP_MAX_RANK 64    /* CP rank r */
+#define GCP_MAX_RANK 256   /* CP rank r (above 64, the gathers take 2 or 4 columns per lane) */
 
 typedef enum gcp_status {
     GCP_OK = 0,
@@ -193,6 +193,17 @@ gcp_status gcp_nz_index_build(const gcp_tensor *X, void *table, int64_t slots,
 size_t gcp_nz_bitmap_bytes(const gcp_tensor *X);
 gcp_status gcp_nz_bitmap_build(const gcp_tensor *X, uint32_t *bitmap, size_t bytes,
                                hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * gcp_set_cols_per_lane -- process-wide tuning choice of how the gradient
+ * kernels lay a sample's r rank columns (eq. Mdef) over a wave: a sample
+ * takes the power of two lps >= ceil(r / cpl) lanes and lane j of them the
+ * cpl columns j, j + lps, ... (cpl = 1, 2 or 4).  0 (the default) picks by rank: 1 for r <= 4, 2
+ * for r <= 16, else 4.  cpl = 1 carries r <= 64, 2 carries 4 < r <= 128, 4
+ * carries 4 < r <= 256; a choice that does not fit a call's rank falls back
+ * to the automatic one.  Results do not depend on it beyond floating-point
+ * summation order.  Returns GCP_ERR_INVALID_ARG for other values. */
+gcp_status gcp_set_cols_per_lane(int32_t cpl);
 
 /* ---------------------------------------------------------------------------
  * gcp_sample -- the sampling lines of Alg. 1 (uniform), Alg. 2 (nonzero picks
@@ -427,7 +438,9 @@ typedef struct gcp_batch_tuning {
     int32_t threads;             /* threads per gradient workgroup: 256, 512 or 1024 (0: 1024) */
     int32_t unit_items;          /* GCP_BATCH_LPT: 64-sample items per work unit (0: 64) */
     int32_t schedule;            /* gcp_batch_schedule */
-    int32_t reserved;
+    int32_t cols_per_lane;       /* rank columns each lane gathers and scatters: 1, 2 or 4
+                                    (0: by rank, as gcp_set_cols_per_lane); a value that
+                                    does not fit a problem's rank falls back to 0 */
 } gcp_batch_tuning;
 
 typedef struct gcp_batch gcp_batch;
@@ -449,6 +462,22 @@ gcp_status gcp_batched_adam_step(gcp_batch *batch, int64_t *state, uint64_t *ite
 gcp_status gcp_batched_plan(const gcp_batch *batch, int64_t *n_blocks, int64_t *n_units,
                             int64_t *block_ptr, int32_t *unit_problem, int64_t *unit_items);
 void gcp_batched_destroy(gcp_batch *batch);
+
+/* gcp_batched_graph_capture -- records `steps` consecutive
+ * gcp_batched_adam_step calls (Alg. 4's inner loop for every problem of the
+ * batch; with iteration_counter, each step draws the next sample sets) into a
+ * HIP graph that the batch owns, and instantiates it.  The arguments (state,
+ * iteration_counter, alpha, beta1, beta2, adam_eps, eps_mode) are fixed at
+ * capture, as in gcp_batched_adam_step.  The steps are recorded on a stream the
+ * library creates for the batch, so nothing runs during the capture.
+ * gcp_batched_graph_launch replays all `steps` on the caller's stream, allocating
+ * nothing.  A new capture replaces the graph; gcp_batched_graph_destroy and
+ * gcp_batched_destroy free it.  The batch must be prepared. */
+gcp_status gcp_batched_graph_capture(gcp_batch *batch, int32_t steps, int64_t *state,
+                                     uint64_t *iteration_counter, double alpha, double beta1,
+                                     double beta2, double adam_eps, gcp_eps_mode eps_mode);
+gcp_status gcp_batched_graph_launch(gcp_batch *batch, hipStream_t stream);
+void gcp_batched_graph_destroy(gcp_batch *batch);
 
 /* ---------------------------------------------------------------------------
  * Kernel timing for measurement harnesses (results never depend on it).

@@ -5,9 +5,9 @@ from . import _lib
 from ._lib import BATCH_CONTIGUOUS, BATCH_LPT
 from .autograd import SampledLoss, sampled_loss
 from .score import factor_match_score
-from .api import (Adam, Batch, FitResult, adam_fit, DataTensor, Factors, LOSSES, Problem, SAMPLERS, SampledAdamStep, SampledGrad,
+from .api import (Adam, Batch, FitResult, adam_fit, DataTensor, Factors, LOSSES, Problem, SAMPLERS, SampledAdamStep, SampledGrad, set_cols_per_lane,
                   coo_tensor, dense_tensor, loss_grad, mttkrp, n_samples, sample, sampled_grad, sampling)
 
 __all__ = ["BATCH_CONTIGUOUS", "BATCH_LPT", "Adam", "Batch", "DataTensor", "Factors", "LOSSES", "Problem", "SAMPLERS", "SampledAdamStep",
            "SampledGrad", "coo_tensor", "dense_tensor", "loss_grad", "mttkrp", "n_samples", "sample",
-           "sampled_grad", "sampling", "SampledLoss", "sampled_loss", "FitResult", "adam_fit", "factor_match_score"]
+           "sampled_grad", "sampling", "set_cols_per_lane", "SampledLoss", "sampled_loss", "FitResult", "adam_fit", "factor_match_score"]

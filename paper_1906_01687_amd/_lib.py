@@ -61,7 +61,7 @@ class GcpProblem(ctypes.Structure):
 
 class GcpBatchTuning(ctypes.Structure):
     _fields_ = [("threads", ctypes.c_int32), ("unit_items", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("cols_per_lane", ctypes.c_int32)]
 
 
 BATCH_CONTIGUOUS, BATCH_LPT = 0, 1
@@ -75,12 +75,13 @@ class GcpFitOptions(ctypes.Structure):
 
 
 EXPORTS = [
-    "gcp_last_error", "gcp_abi_version", "gcp_nz_table_slots", "gcp_nz_table_bytes",
+    "gcp_last_error", "gcp_abi_version", "gcp_set_cols_per_lane", "gcp_nz_table_slots", "gcp_nz_table_bytes",
     "gcp_nz_index_build", "gcp_nz_bitmap_bytes", "gcp_nz_bitmap_build", "gcp_sample_workspace_bytes", "gcp_sample", "gcp_loss_grad",
     "gcp_mttkrp_workspace_bytes", "gcp_mttkrp", "gcp_rejection_status_offset", "gcp_sampled_grad_workspace_bytes",
     "gcp_sampled_grad", "gcp_sampled_grad_noalloc", "gcp_sampled_adam_step", "gcp_adam_step", "gcp_timing_start",
     "gcp_timing_stop", "gcp_batched_create", "gcp_batched_workspace_bytes", "gcp_batched_prepare", "gcp_batched_plan", "gcp_adam_fit_workspace_bytes", "gcp_adam_fit",
-    "gcp_batched_grad", "gcp_batched_adam_step", "gcp_batched_destroy",
+    "gcp_batched_grad", "gcp_batched_adam_step", "gcp_batched_destroy", "gcp_batched_graph_capture",
+    "gcp_batched_graph_launch", "gcp_batched_graph_destroy",
 ]
 
 _lib = None
@@ -100,6 +101,7 @@ def lib() -> ctypes.CDLL:
     sig = {
         "gcp_last_error": (ctypes.c_char_p, []),
         "gcp_abi_version": (ctypes.c_int, []),
+        "gcp_set_cols_per_lane": (st, [ctypes.c_int32]),
         "gcp_nz_table_slots": (i64, [i64]),
         "gcp_nz_table_bytes": (sz, [i64]),
         "gcp_nz_index_build": (st, [T, P, i64, P]),
@@ -129,6 +131,9 @@ def lib() -> ctypes.CDLL:
         "gcp_adam_fit": (st, [ctypes.c_int, P, P, ctypes.POINTER(GcpFitOptions), dbl, P, P, P, P, P, P, P, P,
                               P, P, sz, P]),
         "gcp_batched_destroy": (None, [P]),
+        "gcp_batched_graph_capture": (st, [P, ctypes.c_int32, P, P, dbl, dbl, dbl, dbl, ctypes.c_int]),
+        "gcp_batched_graph_launch": (st, [P, P]),
+        "gcp_batched_graph_destroy": (None, [P]),
         "gcp_timing_start": (st, [i64]),
         "gcp_timing_stop": (st, [ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
     }

@@ -233,6 +233,12 @@ def _ptr_array(tensors) -> ctypes.Array:
 # entry points
 # ---------------------------------------------------------------------------
 
+def set_cols_per_lane(cpl: int) -> None:
+    """gcp_set_cols_per_lane: rank columns per lane of the gradient kernels
+    (1, 2 or 4; 0 picks by rank) for every later single-problem call."""
+    check(lib().gcp_set_cols_per_lane(int(cpl)))
+
+
 def _rejection_status(X: DataTensor, M: Optional["Factors"], cfg: GcpSampling, ws: torch.Tensor) -> int:
     """The rejection status word of a finished call (0: all q zeros drawn; 1:
     the device refill stopped at its cap); 0 for calls without rejection."""
@@ -464,8 +470,9 @@ class Problem:
 
 class Batch:
     """A planned and prepared batch: one gradient launch and one reduction (+ Adam)
-    advance every problem.  ``tune`` = (threads, unit_items[, schedule]) or None
-    for defaults; schedule is BATCH_CONTIGUOUS (default) or BATCH_LPT."""
+    advance every problem.  ``tune`` = (threads, unit_items[, schedule[,
+    cols_per_lane]]) or None for defaults; schedule is BATCH_CONTIGUOUS
+    (default) or BATCH_LPT; cols_per_lane is 1, 2, 4 or 0 (by rank)."""
 
     def __init__(self, problems: Sequence[Problem], tune=None, with_grad: bool = True):
         L = lib()
@@ -475,6 +482,7 @@ class Batch:
         if tune is not None:
             t.threads, t.unit_items = int(tune[0]), int(tune[1])
             t.schedule = int(tune[2]) if len(tune) > 2 else _lib.BATCH_CONTIGUOUS
+            t.cols_per_lane = int(tune[3]) if len(tune) > 3 else 0
         self.tune = tune
         h = ctypes.c_void_p()
         check(L.gcp_batched_create(arr, len(self.problems), ctypes.byref(t), ctypes.byref(h)))
@@ -505,6 +513,18 @@ class Batch:
                   eps_mode: int = _lib.EPS_INSIDE_SQRT, stream=None) -> None:
         check(lib().gcp_batched_adam_step(self.handle, _ptr(self.state), _ptr(self.counter), float(lr),
                                           float(beta1), float(beta2), float(eps), int(eps_mode), _stream(stream)))
+
+    def capture_adam_steps(self, steps: int, lr: float = 0.01, beta1: float = 0.9, beta2: float = 0.999,
+                           eps: float = 1e-8, eps_mode: int = _lib.EPS_INSIDE_SQRT) -> None:
+        """gcp_batched_graph_capture: `steps` batched Adam steps recorded into a
+        graph the batch owns (each step draws the next samples through the
+        batch's iteration counter); replay with graph_launch()."""
+        check(lib().gcp_batched_graph_capture(self.handle, int(steps), _ptr(self.state), _ptr(self.counter),
+                                              float(lr), float(beta1), float(beta2), float(eps), int(eps_mode)))
+
+    def graph_launch(self, stream=None) -> None:
+        """gcp_batched_graph_launch: replay the captured steps on the stream."""
+        check(lib().gcp_batched_graph_launch(self.handle, _stream(stream)))
 
     def close(self) -> None:
         if getattr(self, "handle", None) is not None and self.handle.value:

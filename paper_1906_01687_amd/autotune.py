@@ -2,9 +2,11 @@
 
 The tunables are the gradient workgroup size (256, 512 or 1024 threads), the
 schedule (one contiguous run of items per workgroup, or longest-processing-
-time dealing of units) and, for the latter, the work-unit size (64-sample
-items per unit: small units balance load across workgroups, large ones let a
-workgroup hold more of one problem, so fewer LDS partials are flushed).  Each candidate is planned and prepared as a separate batch whose
+time dealing of units), for the latter the work-unit size (64-sample items
+per unit: small units balance load across workgroups, large ones let a
+workgroup hold more of one problem, so fewer LDS partials are flushed), and
+the rank-chunk shape: how many rank columns each lane of a sample's lane
+group carries (1, 2 or 4, or by rank).  Each candidate is planned and prepared as a separate batch whose
 problems publish no gradient and take no Adam step, timed over a few
 gradient-only steps with the library's dispatch-stamped kernel events, and the
 fastest is kept.  Results are cached in a JSON file keyed by the batch's shape
@@ -24,14 +26,14 @@ import torch
 from . import _lib
 from .api import Batch, Problem
 
-DEFAULT_CANDIDATES: Tuple[Tuple[int, int, int], ...] = tuple(
-    [(t, 0, _lib.BATCH_CONTIGUOUS) for t in (256, 512, 1024)]
-    + [(t, u, _lib.BATCH_LPT) for t in (256, 512, 1024) for u in (16, 64, 256)])
+DEFAULT_CANDIDATES: Tuple[Tuple[int, int, int, int], ...] = tuple(
+    [(t, 0, _lib.BATCH_CONTIGUOUS, c) for t in (512, 1024) for c in (0, 1, 2, 4)]
+    + [(t, u, _lib.BATCH_LPT, c) for t in (256, 512, 1024) for u in (16, 64, 256) for c in (0, 1, 2, 4)])
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "gcp_mi355x", "batch_tuning.json")
 
 
 def signature(problems: Sequence[Problem]) -> str:
-    h = hashlib.sha256()
+    h = hashlib.sha256(b"candidates with cols_per_lane")
     dev = problems[0].M.flat.device
     h.update(torch.cuda.get_device_properties(dev).gcnArchName.encode())
     for p in problems:
@@ -62,7 +64,7 @@ def _time_candidate(problems: Sequence[Problem], tune, steps: int, warmup: int) 
 def tune_batch(problems: Sequence[Problem], candidates: Optional[Iterable[Tuple[int, ...]]] = None,
                steps: int = 10, warmup: int = 2, cache_path: Optional[str] = DEFAULT_CACHE,
                verbose: bool = False) -> Tuple[Tuple[int, ...], Dict[str, float]]:
-    """Best (threads, unit_items, schedule) for this batch and the timings (ms)
+    """Best (threads, unit_items, schedule, cols_per_lane) for this batch and the timings (ms)
     of all candidates; a cached answer for the same signature is returned
     untimed."""
     sig = signature(problems)
@@ -82,7 +84,8 @@ def tune_batch(problems: Sequence[Problem], candidates: Optional[Iterable[Tuple[
         ms = _time_candidate(problems, tune, steps, warmup)
         times["x".join(str(v) for v in tune)] = ms
         if verbose:
-            print(f"[autotune] threads={tune[0]} unit_items={tune[1]} schedule={tune[2] if len(tune) > 2 else 0}: "
+            print(f"[autotune] threads={tune[0]} unit_items={tune[1]} schedule={tune[2] if len(tune) > 2 else 0} "
+                  f"cols_per_lane={tune[3] if len(tune) > 3 else 0}: "
                   f"{ms * 1e3:.1f} us", file=sys.stderr, flush=True)
         if ms < best_ms:
             best, best_ms = tuple(tune), ms

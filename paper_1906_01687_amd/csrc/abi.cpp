@@ -210,7 +210,7 @@ static gcp_status check_factors(const gcp_tensor* X, const gcp_factors* M) {
     if (M->dtype != GCP_F32 && M->dtype != GCP_F64 && M->dtype != GCP_BF16)
         return set_error(GCP_ERR_INVALID_ARG, "M->dtype must be GCP_F32, GCP_F64 or GCP_BF16");
     if (M->rank < 1) return set_error(GCP_ERR_INVALID_ARG, "M->rank must be >= 1");
-    if (M->rank > GCP_MAX_RANK) return set_error(GCP_ERR_UNSUPPORTED, "M->rank above 64 is not supported");
+    if (M->rank > GCP_MAX_RANK) return set_error(GCP_ERR_UNSUPPORTED, "M->rank above 256 is not supported");
     const uint64_t esz = M->dtype == GCP_F64 ? 8 : (M->dtype == GCP_F32 ? 4 : 2);
     for (int k = 0; k < X->d; ++k) {
         if (!M->A[k]) return set_error(GCP_ERR_INVALID_ARG, "M->A[" + std::to_string(k) + "] is NULL");
@@ -444,6 +444,14 @@ gcp_status gcp_nz_bitmap_build(const gcp_tensor* X, uint32_t* bitmap, size_t byt
     return launch_nz_bitmap(X, bitmap, need, stream);
 }
 
+gcp_status gcp_set_cols_per_lane(int32_t cpl) {
+    clear_error();
+    if (cpl != 0 && cpl != 1 && cpl != 2 && cpl != 4)
+        return set_error(GCP_ERR_INVALID_ARG, "cols_per_lane must be 0, 1, 2 or 4");
+    g_cols_per_lane.store(cpl, std::memory_order_relaxed);
+    return GCP_OK;
+}
+
 size_t gcp_sample_workspace_bytes(const gcp_tensor* X, const gcp_sampling* cfg) {
     if (!X || !cfg) return 0;
     Carver c;
@@ -664,6 +672,27 @@ gcp_status gcp_batched_plan(const gcp_batch* batch, int64_t* n_blocks, int64_t* 
 }
 
 void gcp_batched_destroy(gcp_batch* batch) { batch_destroy(batch); }
+
+gcp_status gcp_batched_graph_capture(gcp_batch* batch, int32_t steps, int64_t* state, uint64_t* iteration_counter,
+                                     double alpha, double beta1, double beta2, double adam_eps,
+                                     gcp_eps_mode eps_mode) {
+    clear_error();
+    if (!state) return set_error(GCP_ERR_INVALID_ARG, "state is NULL");
+    if (eps_mode != GCP_EPS_INSIDE_SQRT && eps_mode != GCP_EPS_OUTSIDE_SQRT)
+        return set_error(GCP_ERR_INVALID_ARG, "eps_mode is not a gcp_eps_mode");
+    if (!(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0))
+        return set_error(GCP_ERR_INVALID_ARG, "beta1 and beta2 must be in [0, 1)");
+    if (!(adam_eps >= 0.0) || !(alpha >= 0.0)) return set_error(GCP_ERR_INVALID_ARG, "alpha and eps must be >= 0");
+    const AdamParams ap{nullptr, nullptr, nullptr, nullptr, state, alpha, beta1, beta2, adam_eps, 0.0, (int)eps_mode};
+    return batch_graph_capture(batch, steps, &ap, iteration_counter);
+}
+
+gcp_status gcp_batched_graph_launch(gcp_batch* batch, hipStream_t stream) {
+    clear_error();
+    return batch_graph_launch(batch, stream);
+}
+
+void gcp_batched_graph_destroy(gcp_batch* batch) { batch_graph_destroy(batch); }
 
 // ---------------------------------------------------------------------------
 // GCP-Adam driver (Alg. 4): host control flow over the entry points above.

@@ -141,17 +141,17 @@ struct gcp_batch {
     size_t off_args = 0, off_units = 0, off_bptr = 0, off_f32 = 0, off_red = 0, off_flat = 0, off_acc = 0;
     size_t ws_bytes = 0;
     char* ws = nullptr;
+    // graph of captured steps (gcp_batched_graph_capture) and the stream it
+    // was recorded on
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int32_t graph_steps = 0;
 };
 
 namespace gcp {
 
 constexpr int kXcds = 8;  // accelerator complex dies of an MI355X
-
-static int lps_for(int64_t r) {
-    int l = 1;
-    while (l < r) l <<= 1;
-    return l;
-}
 
 gcp_status batch_create(const gcp_problem* problems, int32_t count, const gcp_batch_tuning* tune, gcp_batch** out,
                         gcp_status (*check_problem)(const gcp_problem*, int32_t)) {
@@ -199,7 +199,6 @@ gcp_status batch_create(const gcp_problem* problems, int32_t count, const gcp_ba
         a.sampler = pr.cfg.sampler;
         a.format = pr.X.format;
         a.r = (int)r;
-        a.lps = lps_for(r);
         a.nnz = pr.X.nnz;
         a.seed = pr.cfg.seed;
         a.pid = pr.cfg.problem_id;
@@ -244,6 +243,8 @@ gcp_status batch_create(const gcp_problem* problems, int32_t count, const gcp_ba
             a.lds_total = 0;
             B->lds_fp32[b] = 0;
         }
+        a.cpl = cols_per_lane(r, tune ? tune->cols_per_lane : 0, a.priv_mask == 0);
+        a.lps = lanes_per_sample(r, a.cpl);
         stratum_weights(&pr.X, &pr.cfg, a.w);
         a.kz = corr_zero_weight(&pr.X, &pr.cfg);
         a.weights = pr.X.weights;
@@ -451,7 +452,59 @@ gcp_status batch_step(gcp_batch* B, const AdamParams* adam, uint64_t* iteration_
     return check_launch("gcp_batched step (reduction)");
 }
 
-void batch_destroy(gcp_batch* B) { delete B; }
+void batch_graph_destroy(gcp_batch* B) {
+    if (!B) return;
+    if (B->exec) (void)hipGraphExecDestroy(B->exec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    B->exec = nullptr;
+    B->graph = nullptr;
+    B->graph_steps = 0;
+}
+
+gcp_status batch_graph_capture(gcp_batch* B, int32_t steps, const AdamParams* adam, uint64_t* iteration_counter) {
+    if (!B || !B->ws) return set_error(GCP_ERR_INVALID_ARG, "batch not prepared (call gcp_batched_prepare)");
+    if (steps < 1) return set_error(GCP_ERR_INVALID_ARG, "steps must be >= 1");
+    batch_graph_destroy(B);
+    // the steps are recorded on a stream of the batch's own (a legacy default
+    // stream cannot be captured); replays go to the caller's stream
+    if (!B->cap_stream && hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        B->cap_stream = nullptr;
+        return check_launch("gcp_batched_graph_capture (stream)");
+    }
+    if (hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return check_launch("gcp_batched_graph_capture (begin)");
+    gcp_status st = GCP_OK;
+    for (int32_t i = 0; i < steps && st == GCP_OK; ++i) st = batch_step(B, adam, iteration_counter, nullptr, nullptr, B->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(B->cap_stream, &g);
+    if (st != GCP_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess || !g) return check_launch("gcp_batched_graph_capture (end)");
+    hipGraphExec_t x = nullptr;
+    if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return check_launch("gcp_batched_graph_capture (instantiate)");
+    }
+    B->graph = g;
+    B->exec = x;
+    B->graph_steps = steps;
+    return GCP_OK;
+}
+
+gcp_status batch_graph_launch(gcp_batch* B, hipStream_t s) {
+    if (!B || !B->exec) return set_error(GCP_ERR_INVALID_ARG, "the batch holds no captured graph");
+    if (hipGraphLaunch(B->exec, s) != hipSuccess) return check_launch("gcp_batched_graph_launch");
+    return GCP_OK;
+}
+
+void batch_destroy(gcp_batch* B) {
+    if (!B) return;
+    batch_graph_destroy(B);
+    if (B->cap_stream) (void)hipStreamDestroy(B->cap_stream);
+    delete B;
+}
 
 int64_t batch_blocks(const gcp_batch* B) { return B ? B->blocks : 0; }
 

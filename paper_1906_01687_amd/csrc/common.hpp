@@ -3,6 +3,8 @@
 // C ABI (abi.cpp) calls after validating its arguments.
 #pragma once
 
+#include <atomic>
+
 #include <hip/hip_runtime_api.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -80,6 +82,17 @@ RejScratch carve_rejection(Carver& c, void* base, int64_t ncand, bool staged, in
 // Group count up to which the fused kernel forms chunk prefixes itself
 // instead of reading a scan.
 constexpr int64_t kMaxGroupsInKernel = 2048;
+
+// Phase-B lane layout: rank columns per lane (1, 2 or 4) and lanes per sample
+// (the power of two >= ceil(r / cpl), at most 64).  hint 0 picks by rank and
+// scatter (or takes the process-wide choice of gcp_set_cols_per_lane); a hint
+// that does not fit r falls back to the automatic choice.  device_atomics:
+// some mode is accumulated with device atomics.
+int cols_per_lane(int64_t r, int hint, bool device_atomics = false);
+int lanes_per_sample(int64_t r, int cpl);
+// Whether cpl columns per lane can carry rank r (every sample fits one wave).
+bool cols_per_lane_fits(int64_t r, int cpl);
+extern std::atomic<int> g_cols_per_lane;
 
 // Multiprocessor count of the current device (cached per device).
 int device_cu_count();
@@ -197,6 +210,9 @@ gcp_status batch_prepare(gcp_batch* b, void* ws, size_t ws_bytes, hipStream_t s)
 gcp_status batch_step(gcp_batch* b, const AdamParams* adam, uint64_t* iteration_counter, hipEvent_t e0, hipEvent_t e1,
                       hipStream_t s);
 void batch_destroy(gcp_batch* b);
+gcp_status batch_graph_capture(gcp_batch* b, int32_t steps, const AdamParams* adam, uint64_t* iteration_counter);
+gcp_status batch_graph_launch(gcp_batch* b, hipStream_t s);
+void batch_graph_destroy(gcp_batch* b);
 int64_t batch_blocks(const gcp_batch* b);
 gcp_status batch_plan(const gcp_batch* b, int64_t* n_blocks, int64_t* n_units, int64_t* block_ptr,
                       int32_t* unit_problem, int64_t* unit_items);

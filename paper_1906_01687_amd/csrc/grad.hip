@@ -264,9 +264,59 @@ void allow_full_lds(const void* kernel) {
         (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
-static int lanes_per_sample(int64_t r) {
+std::atomic<int> g_cols_per_lane{0};
+
+// Stride of the item permutation g -> g * stride mod n: with stratified or
+// semi-stratified sampling the nonzero items (a draw and two dependent
+// gathers each) come first and the zero items (staged by the count kernel, or
+// a draw with no data) after, so in order they would fill whole CUs with one
+// kind; a stride near n / phi coprime to n deals both kinds evenly over the
+// workgroups.  Identity otherwise, or when the products could overflow 64 bits.
+static uint64_t item_stride(int64_t n, bool mixed) {
+    if (!mixed || n < 3 || n >= ((int64_t)1 << 32)) return 1;
+    auto gcd = [](uint64_t x, uint64_t y) {
+        while (y) {
+            const uint64_t t = x % y;
+            x = y;
+            y = t;
+        }
+        return x;
+    };
+    uint64_t s = (uint64_t)((double)n * 0.6180339887498949);
+    if (s < 2) s = 2;
+    while (gcd(s, (uint64_t)n) != 1) ++s;
+    return s % (uint64_t)n;
+}
+
+bool cols_per_lane_fits(int64_t r, int cpl) {
+    if (cpl == 1) return r >= 1 && r <= kWave;
+    // wider chunks pair with lane groups of at least 8 / cpl lanes (r > 4)
+    if (cpl == 2 || cpl == 4) return r > 4 && r <= (int64_t)kWave * cpl;
+    return false;
+}
+
+int cols_per_lane(int64_t r, int hint, bool device_atomics) {
+    if (hint == 0) hint = g_cols_per_lane.load(std::memory_order_relaxed);
+    if (hint != 0 && cols_per_lane_fits(r, hint)) return hint;
+    // Automatic.  Wider layouts spread the per-sample work (broadcast of the
+    // sample, the derivative, the group sum) over more columns, but when r is
+    // not a multiple of lps each further column step is a partly filled
+    // instruction, and a device atomic costs one operation per row sector per
+    // instruction, so a mode on device atomics keeps one column per lane
+    // (measured on MI355X: rank 8 with LDS partials 22.6 -> 21.2 us with two
+    // columns; rank 32 with LDS partials 156 -> 129 us with four; rank 10 with
+    // a device-atomic mode 90 -> 125 us with two).  Ranks above 64 need them.
+    if (r > 2 * kWave) return 4;
+    if (r > kWave) return 2;
+    if (device_atomics || r <= 4) return 1;
+    if (r <= 16) return 2;
+    return 4;
+}
+
+int lanes_per_sample(int64_t r, int cpl) {
+    const int64_t need = (r + cpl - 1) / cpl;
     int l = 1;
-    while (l < r) l <<= 1;
+    while (l < need) l <<= 1;
     return l;
 }
 
@@ -391,7 +441,8 @@ static GradArgs base_args(const gcp_tensor* X, const gcp_factors* M, const Scatt
     for (int k = 0; k < X->d; ++k) a.dims.n[k] = X->dims[k];
     a.format = X->format;
     a.r = (int)M->rank;
-    a.lps = lanes_per_sample(M->rank);
+    a.cpl = cols_per_lane(M->rank, 0, pl.priv_mask != (1u << X->d) - 1u);
+    a.lps = lanes_per_sample(M->rank, a.cpl);
     a.nnz = X->nnz;
     a.values = X->values;
     a.coo = X->coo_idx;
@@ -477,6 +528,9 @@ gcp_status launch_grad_fused(gcp_loss loss, const gcp_tensor* X, const gcp_facto
         }
     }
     a.n_direct_items = (a.n_direct + kWave - 1) / kWave;
+    const bool two_kinds = (cfg->sampler == GCP_SAMPLER_STRATIFIED || cfg->sampler == GCP_SAMPLER_SEMI_STRATIFIED) &&
+                           cfg->p > 0 && cfg->q > 0;
+    a.item_stride = item_stride(a.n_direct_items + a.n_zero_items, two_kinds);
     // with nothing sampled the single workgroup still publishes a zero partial
     dispatch_d(X->d, [&](auto dc) {
         grad_launch<decltype(dc)::value, false>(a, pl, M->dtype, X->vdtype, s, ev_start, ev_stop);
@@ -550,7 +604,8 @@ gcp_status launch_loss_grad(gcp_loss loss, const gcp_tensor* X, const gcp_sampli
     LossArgs a{};
     a.loss = loss;
     a.r = (int)M->rank;
-    a.lps = lanes_per_sample(M->rank);
+    a.cpl = cols_per_lane(M->rank, 0);
+    a.lps = lanes_per_sample(M->rank, a.cpl);
     a.S = S;
     for (int k = 0; k < X->d; ++k) a.n[k] = X->dims[k];
     a.idx = idx;

@@ -15,7 +15,8 @@ struct GradArgs {
     int sampler;
     int format;
     int r;
-    int lps;
+    int lps;  // lanes per sample: the power of two >= ceil(r / cpl)
+    int cpl;  // rank columns per lane: 1, 2 or 4
     int64_t nnz;
     uint64_t seed, pid, iter;
     const uint64_t* iter_ctr;
@@ -24,6 +25,10 @@ struct GradArgs {
     NzTable tab;
     // direct items: samples c in [0, n_direct), 64 per item
     int64_t n_direct, n_direct_items, p;
+    // waves take items in the order g -> (g * item_stride) mod n_items (a
+    // permutation; 0 or 1: in order), so the costlier nonzero items and the
+    // zero items of stratified sampling are spread over all CUs
+    uint64_t item_stride;
     // stratified zeros: one item per chunk of 64 rejection candidates
     int64_t n_zero_items, ncand, q, ngroups;
     const uint32_t* chunk_count;
@@ -340,12 +345,16 @@ __device__ __forceinline__ P* uni(P* p) {
 }
 
 // Per-call constants of phase B: lane layout, buffer descriptors of the
-// factor blocks and scatter bases of the lane's column.
+// factor blocks and scatter bases of the lane's columns.  A sample takes a
+// group of lps lanes; lane j of the group owns columns j, j + lps, ...,
+// j + (cpl - 1) lps, so for every column step the group's lanes touch
+// consecutive elements of a row (coalesced gathers, conflict-free LDS adds,
+// one sector per row for device atomics).  Bit c of cmask says whether
+// column j + c lps exists (< r).
 template <int D, typename LT>
 struct PhaseB {
     int lps, spw, slot, r, loss;
-    uint32_t j, priv;
-    bool colj;
+    uint32_t j, cmask, priv;
     double kz;
     __amdgpu_buffer_rsrc_t rs[D];
     uint32_t lbase[D];
@@ -354,7 +363,23 @@ struct PhaseB {
     bool acc32;
 };
 
-template <int NB, int D, typename FT, bool LIST, typename LT, bool STAGED>
+// Passes per batch for CPL columns per lane: as many as keep a batch's
+// registers (indices, value, weight and gathered entries) within a budget of
+// 48 VGPRs for d <= 3 and 32 beyond (the rest of phase B and the prefetched
+// next sample share the 128 a 1024-thread workgroup allows; these budgets
+// are the largest that compile without spills), and no more than the passes
+// an item has at the smallest lane group the host pairs with CPL (CPL > 1
+// only for r > 4, so lps >= 8 / CPL).
+template <int D, typename T, int CPL>
+constexpr int passes_per_batch() {
+    constexpr int words = D + (2 + D * CPL) * (int)(sizeof(T) / 4);
+    constexpr int budget = D <= 3 ? 48 : 32;
+    constexpr int nb = words * 8 <= budget ? 8 : (words * 4 <= budget ? 4 : (words * 2 <= budget ? 2 : 1));
+    constexpr int cap = CPL == 1 ? 8 : (CPL == 2 ? 4 : 2);
+    return nb < cap ? nb : cap;
+}
+
+template <int NB, int CPL, int D, typename FT, bool LIST, typename LT, bool STAGED>
 __device__ __forceinline__ void pass_batches(const GradArgs& a, const PhaseB<D, LT>& b, LT* __restrict__ lds,
                                              const Sample<D, typename Compute<FT>::type>* stage,
                                              const Sample<D, typename Compute<FT>::type>& smp,
@@ -384,52 +409,80 @@ __device__ __forceinline__ void pass_batches(const GradArgs& a, const PhaseB<D, 
             }
             ww[u] = pass_ok ? wv : T(0);
         }
-        T av[NB][D];
+        T av[NB][D][CPL];
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
 #pragma unroll
             for (int k = 0; k < D; ++k) {
-                const T v = RowLoad<FT>::at(b.rs[k], qq[u][k] + b.j);
-                av[u][k] = b.colj ? v : T(0);
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    const T v = RowLoad<FT>::at(b.rs[k], qq[u][k] + b.j + (uint32_t)(c * b.lps));
+                    av[u][k][c] = ((b.cmask >> c) & 1u) ? v : T(0);
+                }
             }
         }
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
-            T pre[D], suf[D];
-            pre[0] = T(1);
+            // leave-one-out products of every column from prefix and suffix products
+            T pre[D][CPL], suf[D][CPL];
+            T part = T(0);
 #pragma unroll
-            for (int k = 1; k < D; ++k) pre[k] = pre[k - 1] * av[u][k - 1];
-            suf[D - 1] = T(1);
+            for (int c = 0; c < CPL; ++c) {
+                pre[0][c] = T(1);
 #pragma unroll
-            for (int k = D - 2; k >= 0; --k) suf[k] = suf[k + 1] * av[u][k + 1];
+                for (int k = 1; k < D; ++k) pre[k][c] = pre[k - 1][c] * av[u][k - 1][c];
+                suf[D - 1][c] = T(1);
+#pragma unroll
+                for (int k = D - 2; k >= 0; --k) suf[k][c] = suf[k + 1][c] * av[u][k + 1][c];
+                part += pre[D - 1][c] * av[u][D - 1][c];
+            }
             const bool live = carries(ww[u]);
             T y;
             if constexpr (LIST) {
                 y = xx[u];
             } else {
-                const T m = group_sum(pre[D - 1] * av[u][D - 1], b.lps);
+                const T m = group_sum(part, b.lps);
                 y = weighted_g(b.loss, xx[u], m, ww[u], eps, (T)b.kz);
                 if (a.loss_sum && live && b.j == 0) fsum += weighted_f(b.loss, xx[u], m, ww[u], eps, (T)b.kz);
             }
-            if (live && b.colj) {
+            if (live && b.cmask) {
 #pragma unroll
                 for (int k = 0; k < D; ++k) {
-                    const T v = y * (pre[k] * suf[k]);
-                    if ((b.priv >> k) & 1u)
-                        lds_add(reinterpret_cast<LT*>(reinterpret_cast<char*>(lds) + b.lbase[k] +
-                                                      qq[u][k] * (uint32_t)sizeof(LT)),
-                                (LT)v);
-                    else {
-                        uint32_t row = qq[u][k];
-                        if (b.acc_magic) row = __umulhi(row, b.acc_magic) * b.acc_stride;
-                        if (b.acc32)
-                            unsafeAtomicAdd(static_cast<float*>(b.accj[k]) + row, (float)v);
+                    uint32_t row = qq[u][k];
+                    if (!((b.priv >> k) & 1u) && b.acc_magic) row = __umulhi(row, b.acc_magic) * b.acc_stride;
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        if (!((b.cmask >> c) & 1u)) continue;
+                        const T v = y * (pre[k][c] * suf[k][c]);
+                        const uint32_t cc = (uint32_t)(c * b.lps);
+                        if ((b.priv >> k) & 1u)
+                            lds_add(reinterpret_cast<LT*>(reinterpret_cast<char*>(lds) + b.lbase[k] +
+                                                          (qq[u][k] + cc) * (uint32_t)sizeof(LT)),
+                                    (LT)v);
+                        else if (b.acc32)
+                            unsafeAtomicAdd(static_cast<float*>(b.accj[k]) + (row + cc), (float)v);
                         else
-                            unsafeAtomicAdd(static_cast<double*>(b.accj[k]) + row, (double)v);
+                            unsafeAtomicAdd(static_cast<double*>(b.accj[k]) + (row + cc), (double)v);
                     }
                 }
             }
         }
+    }
+}
+
+template <int CPL, int D, typename FT, bool LIST, typename LT, bool STAGED>
+__device__ __forceinline__ void run_passes(const GradArgs& a, const PhaseB<D, LT>& b, LT* __restrict__ lds,
+                                           const Sample<D, typename Compute<FT>::type>* stage,
+                                           const Sample<D, typename Compute<FT>::type>& smp,
+                                           typename Compute<FT>::type& fsum) {
+    using T = typename Compute<FT>::type;
+    constexpr int nb = passes_per_batch<D, T, CPL>();
+    if constexpr (CPL == 1 && nb == 8) {
+        // lane groups of at most 4 lanes have at most 4 passes per item
+        if (b.lps <= 4) pass_batches<4, 1, D, FT, LIST, LT, STAGED>(a, b, lds, stage, smp, fsum);
+        else pass_batches<8, 1, D, FT, LIST, LT, STAGED>(a, b, lds, stage, smp, fsum);
+    } else {
+        pass_batches<nb, CPL, D, FT, LIST, LT, STAGED>(a, b, lds, stage, smp, fsum);
     }
 }
 
@@ -439,12 +492,13 @@ __device__ __forceinline__ void pass_batches(const GradArgs& a, const PhaseB<D, 
 // With a staging slice (64 records of this wave in LDS), each pass reads its
 // sample's record with wide broadcast reads; without one it broadcasts with
 // ds_bpermute (about six times the LDS time per word, measured).
-// A sample takes a group of lps lanes, lane j holding column j of its rows, so
-// one pass covers 64/lps samples.  Passes are taken 2 to 8 at a time so that
-// the row gathers of a batch are all in flight before any of them is
-// consumed.  Every lane of the wave must call this.
-// PADDED_ACC = false fixes the device accumulator to FP64 rows of r (the
-// batched kernel's layout), so none of the padded-row code is generated.
+// A sample takes a group of lps lanes, lane j holding columns j, j + lps, ..
+// of its rows, so one pass covers 64/lps samples; the model entry's column
+// sum is taken over the lane's columns, then over the group.  Passes are taken 1 to 8 at a time so that the row gathers of a batch
+// are all in flight before any of them is consumed.  Every lane of the wave
+// must call this.  PADDED_ACC = false fixes the device accumulator to FP64
+// rows of r (the batched kernel's layout), so none of the padded-row code is
+// generated.
 template <int D, typename FT, bool LIST, typename LT = double, bool PADDED_ACC = true>
 __device__ __forceinline__ void evaluate_and_scatter(const GradArgs& a, LT* __restrict__ lds,
                                                      Sample<D, typename Compute<FT>::type>* stage,
@@ -456,10 +510,13 @@ __device__ __forceinline__ void evaluate_and_scatter(const GradArgs& a, LT* __re
     b.spw = kWave / b.lps;
     b.slot = lane / b.lps;
     b.j = (uint32_t)(lane & (b.lps - 1));
+    const int cpl = uni((int32_t)a.cpl);
     b.r = uni((int32_t)a.r);
+    b.cmask = 0;
+    for (int c = 0; c < cpl; ++c)
+        if ((int)b.j + c * b.lps < b.r) b.cmask |= 1u << c;
     b.loss = uni((int32_t)a.loss);
     b.priv = uni(a.priv_mask);
-    b.colj = (int)b.j < b.r;
     b.kz = a.kz;
     char* const acc = reinterpret_cast<char*>(uni(a.acc));
     if constexpr (PADDED_ACC) {
@@ -481,29 +538,18 @@ __device__ __forceinline__ void evaluate_and_scatter(const GradArgs& a, LT* __re
         b.lbase[k] = (uint32_t)((uni(a.lds_off[k]) + (int64_t)b.j) * (int64_t)sizeof(LT));
         b.accj[k] = acc ? acc + (uni(a.acc_off[k]) + (int64_t)b.j) * acc_elem : nullptr;
     }
-    // passes per batch: as many as keep a batch's registers (indices, value,
-    // weight and gathered entries) within about 64 VGPRs
-    using T = typename Compute<FT>::type;
-    constexpr int words = D + (2 + D) * (int)(sizeof(T) / 4);
-    constexpr int nb = words * 8 <= 64 ? 8 : (words * 4 <= 64 ? 4 : 2);
     if (uni(a.stage_off) != kNoStage) {
         // the wave's own slice: ds operations of one wave complete in order, so
         // the reads below see these writes and the next item's writes cannot
         // overtake them
         stage[lane] = smp;
-        if constexpr (nb == 8) {
-            if (b.lps <= 4) pass_batches<4, D, FT, LIST, LT, true>(a, b, lds, stage, smp, fsum);
-            else pass_batches<8, D, FT, LIST, LT, true>(a, b, lds, stage, smp, fsum);
-        } else {
-            pass_batches<nb, D, FT, LIST, LT, true>(a, b, lds, stage, smp, fsum);
-        }
+        if (cpl == 1) run_passes<1, D, FT, LIST, LT, true>(a, b, lds, stage, smp, fsum);
+        else if (cpl == 2) run_passes<2, D, FT, LIST, LT, true>(a, b, lds, stage, smp, fsum);
+        else run_passes<4, D, FT, LIST, LT, true>(a, b, lds, stage, smp, fsum);
     } else {
-        if constexpr (nb == 8) {
-            if (b.lps <= 4) pass_batches<4, D, FT, LIST, LT, false>(a, b, lds, stage, smp, fsum);
-            else pass_batches<8, D, FT, LIST, LT, false>(a, b, lds, stage, smp, fsum);
-        } else {
-            pass_batches<nb, D, FT, LIST, LT, false>(a, b, lds, stage, smp, fsum);
-        }
+        if (cpl == 1) run_passes<1, D, FT, LIST, LT, false>(a, b, lds, stage, smp, fsum);
+        else if (cpl == 2) run_passes<2, D, FT, LIST, LT, false>(a, b, lds, stage, smp, fsum);
+        else run_passes<4, D, FT, LIST, LT, false>(a, b, lds, stage, smp, fsum);
     }
 }
 

@@ -92,10 +92,14 @@ __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
     const int64_t n_items = a.n_direct_items + a.n_zero_items;
     const uint64_t iter = effective_iteration(a.iter, a.iter_ctr);
     T fsum = T(0);
+    const uint64_t stride = a.item_stride;
+    auto item_at = [&](int64_t g) -> int64_t {
+        return stride > 1 ? (int64_t)(((uint64_t)g * stride) % (uint64_t)n_items) : g;
+    };
 
     // the first item's draws and gathers are issued before the LDS clear, so
     // the clear runs under their latency
-    Sample<D, T> cur = wave < n_items ? item_sample<D, FT, VT, LIST>(a, iter, wave) : no_sample<D, T>();
+    Sample<D, T> cur = wave < n_items ? item_sample<D, FT, VT, LIST>(a, iter, item_at(wave)) : no_sample<D, T>();
     {
         constexpr int per16 = 16 / sizeof(LT);
         uint4* l16 = reinterpret_cast<uint4*>(lds_raw);
@@ -105,10 +109,11 @@ __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
     }
     __syncthreads();
 
-    for (int64_t item = wave; item < n_items; item += nwave) {
+    for (int64_t g = wave; g < n_items; g += nwave) {
+        const int64_t item = item_at(g);
         // the next item's gathers are in flight while this one is evaluated
-        const int64_t next = item + nwave;
-        Sample<D, T> nxt = next < n_items ? item_sample<D, FT, VT, LIST>(a, iter, next) : no_sample<D, T>();
+        const int64_t next = g + nwave;
+        Sample<D, T> nxt = next < n_items ? item_sample<D, FT, VT, LIST>(a, iter, item_at(next)) : no_sample<D, T>();
         to_rows(a, cur);
         evaluate_and_scatter<D, FT, LIST>(a, lds, stage, cur, fsum);
         if constexpr (!LIST) {
@@ -178,7 +183,7 @@ __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
 // forms m with a VALU group sum, and lane 0 of the group writes ytilde and
 // adds its weighted loss.
 // ---------------------------------------------------------------------------
-template <int NB, int D, typename FT>
+template <int NB, int CPL, int D, typename FT>
 __device__ __forceinline__ void loss_passes(const LossArgs& a, const __amdgpu_buffer_rsrc_t (&rs)[D], int64_t item,
                                             const Sample<D, typename Compute<FT>::type>* stage,
                                             typename Compute<FT>::type& fsum) {
@@ -186,7 +191,6 @@ __device__ __forceinline__ void loss_passes(const LossArgs& a, const __amdgpu_bu
     const int lane = threadIdx.x & (kWave - 1);
     const int lps = a.lps, spw = kWave / lps, slot = lane / lps;
     const uint32_t j = (uint32_t)(lane & (lps - 1));
-    const bool colj = (int)j < a.r;
     const T eps = (T)a.eps;
     for (int p0 = 0; p0 < lps; p0 += NB) {
         uint32_t qq[NB][D];
@@ -204,10 +208,17 @@ __device__ __forceinline__ void loss_passes(const LossArgs& a, const __amdgpu_bu
         T prod[NB];
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
-            prod[u] = T(1);
+            T pc[CPL];
 #pragma unroll
-            for (int k = 0; k < D; ++k) prod[u] *= RowLoad<FT>::at(rs[k], qq[u][k] + j);
-            prod[u] = colj ? prod[u] : T(0);
+            for (int c = 0; c < CPL; ++c) pc[c] = T(1);
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) pc[c] *= RowLoad<FT>::at(rs[k], qq[u][k] + j + (uint32_t)(c * lps));
+            }
+            prod[u] = T(0);
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) prod[u] += ((int)j + c * lps < a.r) ? pc[c] : T(0);
         }
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
@@ -270,13 +281,14 @@ __global__ __launch_bounds__(256) void loss_grad_kernel(LossArgs a) {
         }
         // this wave's slice; its ds operations complete in order
         stage[lane] = smp;
-        constexpr int words = D + (2 + D) * (int)(sizeof(T) / 4);
-        constexpr int nb = words * 8 <= 64 ? 8 : (words * 4 <= 64 ? 4 : 2);
-        if constexpr (nb == 8) {
-            if (a.lps <= 4) loss_passes<4, D, FT>(a, rs, item, stage, fsum);
-            else loss_passes<8, D, FT>(a, rs, item, stage, fsum);
+        if (a.cpl == 1) {
+            constexpr int nb = passes_per_batch<D, T, 1>();
+            if (nb == 8 && a.lps <= 4) loss_passes<4, 1, D, FT>(a, rs, item, stage, fsum);
+            else loss_passes<nb, 1, D, FT>(a, rs, item, stage, fsum);
+        } else if (a.cpl == 2) {
+            loss_passes<passes_per_batch<D, T, 2>(), 2, D, FT>(a, rs, item, stage, fsum);
         } else {
-            loss_passes<nb, D, FT>(a, rs, item, stage, fsum);
+            loss_passes<passes_per_batch<D, T, 4>(), 4, D, FT>(a, rs, item, stage, fsum);
         }
     }
     if (a.loss_sum) {

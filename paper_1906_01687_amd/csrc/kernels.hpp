@@ -18,6 +18,7 @@ struct LossArgs {
     int loss;
     int r;
     int lps;
+    int cpl;
     int64_t S;
     int64_t n[GCP_MAX_D];
     const uint32_t* idx;

@@ -103,7 +103,7 @@ def test_argument_errors_are_reported_without_launching():
     t = _dense_struct(m, (3, 4))
     M = m.GcpFactors()
     M.dtype = m.F32
-    M.rank = 65
+    M.rank = 257
     M.A[0] = M.A[1] = 0x1000
     G = (ctypes.c_void_p * 2)(0x1000, 0x1000)
     st = L.gcp_sampled_grad(0, ctypes.byref(t), ctypes.byref(M), ctypes.byref(cfg), 1e-10, G, None,
@@ -388,3 +388,12 @@ def test_noalloc_refuses_problems_beyond_its_scratch():
     G = (ctypes.c_void_p * 3)(0x1000, 0x1000, 0x1000)
     st = L.gcp_sampled_grad_noalloc(0, ctypes.byref(t), ctypes.byref(M), ctypes.byref(cfg), 1e-10, G, None, None)
     assert st == 4 and b"static" in L.gcp_last_error(), L.gcp_last_error()
+
+
+def test_cols_per_lane_setter():
+    m = _lib()
+    L = m.lib()
+    for bad in (3, 8, -1):
+        assert L.gcp_set_cols_per_lane(bad) == 1
+    for ok in (1, 2, 4, 0):
+        assert L.gcp_set_cols_per_lane(ok) == 0

@@ -74,7 +74,9 @@ def oracle_gradient(w, pid, iteration, dtype):
 
 
 @pytest.mark.parametrize("tune", [None, (256, 0, gcp.BATCH_CONTIGUOUS), (512, 0, gcp.BATCH_CONTIGUOUS),
-                                  (256, 8, gcp.BATCH_LPT), (512, 1, gcp.BATCH_LPT), (1024, 200, gcp.BATCH_LPT)])
+                                  (256, 8, gcp.BATCH_LPT), (512, 1, gcp.BATCH_LPT), (1024, 200, gcp.BATCH_LPT),
+                                  (1024, 64, gcp.BATCH_LPT, 1), (512, 16, gcp.BATCH_LPT, 2),
+                                  (1024, 0, gcp.BATCH_CONTIGUOUS, 4)])
 def test_batched_grad_matches_single_problem_calls(tune):
     announce(f"batched gradient vs single-problem calls and the oracle, tune={tune}")
     ws = mixed_workloads()
@@ -152,6 +154,38 @@ def test_batched_graph_replay():
         for b in range(len(ws)):
             torch.testing.assert_close(pa[b].M.flat, pb[b].M.flat, rtol=1e-5, atol=1e-7)
         _ = sum(float(p.M.flat.sum()) for p in pa)   # unrelated eager work between replays
+    ba.close()
+    bb.close()
+
+
+def test_library_graph_replay_equals_eager_steps():
+    """gcp_batched_graph_capture / _launch: a library-owned graph of 3 batched
+    Adam steps, replayed twice with eager work in between, equals 6 eager
+    steps (the iteration counter gives every replayed step fresh samples)."""
+    announce("library-owned graph of batched Adam steps vs eager steps")
+    ws = mixed_workloads()[:7]
+    pa = [make_problem(w, b) for b, w in enumerate(ws)]
+    pb = [make_problem(w, b) for b, w in enumerate(ws)]
+    ba, bb = gcp.Batch(pa), gcp.Batch(pb)
+    ba.capture_adam_steps(3, lr=0.02)
+    torch.cuda.synchronize()
+    assert int(ba.counter.item()) == 0 and int(ba.state[0].item()) == 0     # capture ran nothing
+    for rep in range(2):
+        ba.graph_launch()
+        for _ in range(3):
+            bb.adam_step(lr=0.02)
+        torch.cuda.synchronize()
+        assert int(ba.counter.item()) == int(bb.counter.item()) == 3 * (rep + 1)
+        assert int(ba.state[0].item()) == int(bb.state[0].item()) == 3 * (rep + 1)
+        for b in range(len(ws)):
+            torch.testing.assert_close(pa[b].M.flat, pb[b].M.flat, rtol=1e-5, atol=1e-7)
+        _ = sum(float(p.M.flat.sum()) for p in pa)   # unrelated eager work between replays
+    ba.capture_adam_steps(1, lr=0.02)                # a new capture replaces the graph
+    ba.graph_launch()
+    bb.adam_step(lr=0.02)
+    torch.cuda.synchronize()
+    for b in range(len(ws)):
+        torch.testing.assert_close(pa[b].M.flat, pb[b].M.flat, rtol=1e-5, atol=1e-7)
     ba.close()
     bb.close()
 

@@ -168,6 +168,12 @@ CASES = [
     ("counts_semi_zero_factors", lambda: with_zero_factors(small_sparse("counts", rank=10))),
     ("dense_f32_bernoulli_zero_factors", lambda: with_zero_factors(small_dense(rank=6, loss=synth.BERNOULLI_ODDS))),
     ("dense_f32_poisson_zero_factors", lambda: with_zero_factors(small_dense(rank=4, loss=synth.POISSON))),
+    # ranks above one wave's 64 lanes: 2 or 4 columns per lane, with wide
+    # loads (r a multiple of the chunk) and with one load per column
+    ("dense_f32_r100", lambda: small_dense(dims=(23, 19, 17), rank=100, s=3000)),
+    ("dense_f64_r65", lambda: small_dense(dims=(11, 9, 8), rank=65, s=1500, dtype="f64")),
+    ("counts_semi_r130", lambda: small_sparse("counts", dims=(30, 7, 11, 13), rank=130, p=900, q=1100)),
+    ("dense_bf16_r256", lambda: small_dense(dims=(9, 8, 7), rank=256, s=700, dtype="bf16")),
 ]
 
 
@@ -370,3 +376,37 @@ def test_full_size_workload(make):
     np.testing.assert_array_equal(u32(idx), smp.idx)
     np.testing.assert_array_equal(xval.to(torch.float64).cpu().numpy(), smp.xval)
     check_grad(Gg, Gref, oracle_scale(pb, smp), 1e-5, f"full-size {w.name}")
+
+
+VARIANT_CASES = [c for c in CASES if c[0] in (
+    "dense_f32_r5", "binary_strat_r7", "binary_semi_r8", "counts_semi_r10", "counts_strat_r33", "dense_f32_d5_r16",
+    "dense_f64_d2_r2", "counts_semi_fp32_lds", "dense_bf16_r64_fp32_lds", "counts_semi_long_mode_r10",
+    "dense_f64_long_mode_r5", "counts_strat_gamma_r5")]
+
+
+@pytest.mark.parametrize("cpl", [1, 2, 4])
+@pytest.mark.parametrize("name,make", VARIANT_CASES, ids=[c[0] for c in VARIANT_CASES])
+def test_cols_per_lane_variants(name, make, cpl):
+    """Every lane layout (1, 2 or 4 rank columns per lane, where it fits the
+    rank) gives the oracle's gradient, fused and unfused."""
+    announce(f"cols_per_lane={cpl}: {name}")
+    w = make()
+    pb = to_device(w)
+    gcp.set_cols_per_lane(cpl)
+    try:
+        cfg = cfg_for(pb, iteration=4)
+        G, fs = gcp.sampled_grad(w.loss, pb.X, pb.M, cfg, with_loss=True)
+        G = [g.clone() for g in G]
+        idx, y, fs2, G2 = _unfused(pb, cfg)
+        smp = oracle_samples(pb, iteration=4)
+        Gref, Fref, yref = oracle_grad(pb, smp)
+        torch.cuda.synchronize()
+    finally:
+        gcp.set_cols_per_lane(0)
+    tol = TOL[w.dtype]
+    E = oracle_scale(pb, smp)
+    check_grad(G, Gref, E, tol, f"fused cpl={cpl} {name}")
+    check_grad(G2, Gref, E, tol, f"unfused cpl={cpl} {name}")
+    yg = y.to(torch.float64).cpu().numpy()
+    assert np.linalg.norm(yg - yref) <= tol * np.linalg.norm(yref)
+    assert abs(fs.item() - Fref) <= 10 * tol * max(1.0, abs(Fref))
