@@ -260,6 +260,14 @@ size_t gcp_mttkrp_workspace_bytes(const gcp_tensor *X, const gcp_factors *M, int
 gcp_status gcp_mttkrp(const gcp_tensor *X, const gcp_factors *M, const uint32_t *idx,
                       const void *ytilde, int64_t S, void *const *G, int accumulate,
                       void *ws, size_t ws_bytes, hipStream_t stream);
+/* gcp_mttkrp_scaled -- gcp_mttkrp with every G_k scaled by the device scalar
+ * *scale (nullable: 1), read on the device when the reduction runs: the
+ * adjoint of a sampled loss F(A) (eq. Gks) times an upstream derivative that
+ * lives in device memory, with no host round trip.  With accumulate, G_k +=
+ * scale * MTTKRP. */
+gcp_status gcp_mttkrp_scaled(const gcp_tensor *X, const gcp_factors *M, const uint32_t *idx,
+                             const void *ytilde, int64_t S, void *const *G, int accumulate,
+                             const double *scale, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Byte offset, in the workspace of a STRATIFIED call with q > 0, of the
  * rejection status word (uint32): 0 once the call has drawn all q zeros, 1 if
@@ -319,6 +327,12 @@ gcp_status gcp_sampled_adam_step(gcp_loss loss, const gcp_tensor *X, const gcp_f
                                  double beta2, double adam_eps, double lower,
                                  gcp_eps_mode eps_mode, void *const *G, double *loss_sum,
                                  void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* gcp_bf16_round -- dst[e] = src[e] rounded to bf16 (round to nearest, ties
+ * to even), e < P: the BF16 gather copy of FP32 master factors (the storage
+ * reading of the BF16 factors; the same rounding gcp_adam_step applies after
+ * each update).  dst holds P uint16 bf16 values. */
+gcp_status gcp_bf16_round(int64_t P, const float *src, void *dst, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * gcp_adam_step -- one Adam step with projection over P parameters at once
@@ -391,7 +405,11 @@ gcp_status gcp_adam_fit(gcp_loss loss, const gcp_tensor *X, const gcp_factors *M
  *
  * gcp_problem describes one problem: its data X, factors M (M.A[k] must be
  * the mode-k blocks of the flat array A), sampling cfg (UNIFORM or
- * SEMI_STRATIFIED; cfg.iteration is the problem's base iteration and
+ * SEMI_STRATIFIED; STRATIFIED is refused with GCP_ERR_UNSUPPORTED, since its
+ * zeros come from a rejection pass whose counts must be scanned before the
+ * gradient launch (Alg. 2), a third launch per step, while semi-stratified
+ * sampling serves sparse problems in a batch with the same variance (Sec.
+ * 5.4, Table 1) and no such pass; cfg.iteration is the problem's base iteration and
  * cfg.iteration_counter is ignored -- the batch call takes one counter for
  * all problems), loss and its eps, the Adam projection bound `lower`, and the
  * flat parameter, moment and (nullable) gradient arrays.  All problems of a

@@ -77,7 +77,7 @@ class GcpFitOptions(ctypes.Structure):
 EXPORTS = [
     "gcp_last_error", "gcp_abi_version", "gcp_set_cols_per_lane", "gcp_nz_table_slots", "gcp_nz_table_bytes",
     "gcp_nz_index_build", "gcp_nz_bitmap_bytes", "gcp_nz_bitmap_build", "gcp_sample_workspace_bytes", "gcp_sample", "gcp_loss_grad",
-    "gcp_mttkrp_workspace_bytes", "gcp_mttkrp", "gcp_rejection_status_offset", "gcp_sampled_grad_workspace_bytes",
+    "gcp_mttkrp_workspace_bytes", "gcp_mttkrp", "gcp_mttkrp_scaled", "gcp_bf16_round", "gcp_rejection_status_offset", "gcp_sampled_grad_workspace_bytes",
     "gcp_sampled_grad", "gcp_sampled_grad_noalloc", "gcp_sampled_adam_step", "gcp_adam_step", "gcp_timing_start",
     "gcp_timing_stop", "gcp_batched_create", "gcp_batched_workspace_bytes", "gcp_batched_prepare", "gcp_batched_plan", "gcp_adam_fit_workspace_bytes", "gcp_adam_fit",
     "gcp_batched_grad", "gcp_batched_adam_step", "gcp_batched_destroy", "gcp_batched_graph_capture",
@@ -112,6 +112,8 @@ def lib() -> ctypes.CDLL:
         "gcp_loss_grad": (st, [ctypes.c_int, T, S, M, P, P, P, i64, dbl, P, P, P]),
         "gcp_mttkrp_workspace_bytes": (sz, [T, M, i64]),
         "gcp_mttkrp": (st, [T, M, P, P, i64, P, ctypes.c_int, P, sz, P]),
+        "gcp_mttkrp_scaled": (st, [T, M, P, P, i64, P, ctypes.c_int, P, P, sz, P]),
+        "gcp_bf16_round": (st, [i64, P, P, P]),
         "gcp_rejection_status_offset": (i64, [T, M, S]),
         "gcp_sampled_grad_workspace_bytes": (sz, [T, M, S]),
         "gcp_sampled_grad": (st, [ctypes.c_int, T, M, S, dbl, P, P, P, sz, P]),

@@ -7,14 +7,18 @@ of ytilde_i = w_i g(x_i, m_i) (eqs. mttkrp, Gks), so:
 
 * forward  = gcp_sample (draws, data lookup, strata) + gcp_loss_grad (model
   entries, ytilde and the loss estimate);
-* backward = gcp_mttkrp of the saved ytilde at the saved indices, times the
-  incoming gradient.
+* backward = gcp_mttkrp_scaled of the saved ytilde at the saved indices,
+  scaled on the device by the incoming gradient.
 
-The differentiable input is the flat parameter vector of a ``Factors`` set:
-``flat`` for FP64 and FP32 storage, the FP32 ``master`` for BF16 storage (the
-gathers then read the BF16 copy ``flat``, refreshed from the master at every
-forward).  Gradients come back in the parameter's dtype (FP32 accumulation for
-FP32 and BF16 storage, FP64 for FP64).
+The differentiable input is a flat parameter vector laid out like a
+``Factors`` set: normally ``flat`` itself for FP64 and FP32 storage and the
+FP32 ``master`` for BF16 storage.  The kernels read the Factors storage, so a
+forward on another tensor first copies it there (FP64/FP32), and for BF16
+storage every forward refreshes the BF16 gather copy ``flat`` from the
+parameter with gcp_bf16_round.  The parameter is saved for backward, so an
+in-place change between forward and backward raises instead of giving the
+gradient at other factors.  Gradients come back in the parameter's dtype (FP32
+accumulation for FP32 and BF16 storage, FP64 for FP64).
 
 With ``cfg.iteration_counter`` set, every forward draws a fresh sample set and
 advances the counter on the device; without it the samples are fixed by
@@ -37,19 +41,25 @@ class _SampledLossFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, param: torch.Tensor, sl: "SampledLoss"):
         M = sl.M
+        want = torch.float32 if M.master is not None else M.dtype
+        if param.dtype != want or param.numel() != M.P or param.device != M.flat.device:
+            raise ValueError(f"param must be a {want} vector of {M.P} values on {M.flat.device}")
         if M.master is not None:
-            # BF16 storage: the gathers read the rounded copy of the FP32 master
-            M.flat.copy_(param.detach().to(torch.bfloat16))
+            # BF16 storage: the gathers read the rounded copy of the FP32 parameter
+            check(lib().gcp_bf16_round(M.P, _ptr(param.detach()), _ptr(M.flat), _stream(None)))
+        elif param.data_ptr() != M.flat.data_ptr():
+            M.flat.copy_(param.detach())
         idx, y, fs = sl._forward()
         ctx.sl = sl
-        ctx.save_for_backward(idx, y)
+        ctx.save_for_backward(param, idx, y)
         return fs.view(())
 
     @staticmethod
     def backward(ctx, grad_out: torch.Tensor):
-        idx, y = ctx.saved_tensors
-        G = ctx.sl._backward(idx, y)
-        return G.mul_(grad_out.to(G.dtype)), None
+        _, idx, y = ctx.saved_tensors
+        scale = grad_out.detach().to(torch.float64).reshape(1).contiguous()
+        G = ctx.sl._backward(idx, y, scale=scale)
+        return G, None
 
 
 class SampledLoss:
@@ -95,12 +105,13 @@ class SampledLoss:
                               _ptr(idx), _ptr(xval), _ptr(st), S, self.eps, _ptr(y), _ptr(fs), s))
         return idx, y, fs
 
-    def _backward(self, idx: torch.Tensor, y: torch.Tensor, stream=None) -> torch.Tensor:
+    def _backward(self, idx: torch.Tensor, y: torch.Tensor, scale: Optional[torch.Tensor] = None,
+                  stream=None) -> torch.Tensor:
         L = lib()
         G = self.M.grad_buffer()
-        check(L.gcp_mttkrp(ctypes.byref(self.t), ctypes.byref(self.m), _ptr(idx), _ptr(y), self.S,
-                           _ptr_array(self.M.grad_views(G)), 0, _ptr(self.mttkrp_ws), self.mttkrp_bytes,
-                           _stream(stream)))
+        check(L.gcp_mttkrp_scaled(ctypes.byref(self.t), ctypes.byref(self.m), _ptr(idx), _ptr(y), self.S,
+                                  _ptr_array(self.M.grad_views(G)), 0, _ptr(scale), _ptr(self.mttkrp_ws),
+                                  self.mttkrp_bytes, _stream(stream)))
         return G
 
 

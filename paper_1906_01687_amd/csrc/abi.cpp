@@ -515,8 +515,9 @@ size_t gcp_mttkrp_workspace_bytes(const gcp_tensor* X, const gcp_factors* M, int
     return mttkrp_ws(X, M, S, nullptr, nullptr, nullptr, nullptr);
 }
 
-gcp_status gcp_mttkrp(const gcp_tensor* X, const gcp_factors* M, const uint32_t* idx, const void* ytilde, int64_t S,
-                      void* const* G, int accumulate, void* ws, size_t ws_bytes, hipStream_t stream) {
+gcp_status gcp_mttkrp_scaled(const gcp_tensor* X, const gcp_factors* M, const uint32_t* idx, const void* ytilde,
+                             int64_t S, void* const* G, int accumulate, const double* scale, void* ws,
+                             size_t ws_bytes, hipStream_t stream) {
     clear_error();
     if (gcp_status st = check_tensor(X)) return st;
     if (gcp_status st = check_factors(X, M)) return st;
@@ -533,7 +534,12 @@ gcp_status gcp_mttkrp(const gcp_tensor* X, const gcp_factors* M, const uint32_t*
     mttkrp_ws(X, M, S, ws, &pl, &acc, &partials);
     if (gcp_status st = launch_fill_zero(acc, acc_words(pl), stream)) return st;
     if (gcp_status st = launch_grad_list(X, M, idx, ytilde, S, pl, acc, partials, stream)) return st;
-    return launch_reduce(M, pl, acc, partials, G, accumulate, nullptr, nullptr, stream);
+    return launch_reduce(M, pl, acc, partials, G, accumulate, nullptr, nullptr, stream, scale);
+}
+
+gcp_status gcp_mttkrp(const gcp_tensor* X, const gcp_factors* M, const uint32_t* idx, const void* ytilde, int64_t S,
+                      void* const* G, int accumulate, void* ws, size_t ws_bytes, hipStream_t stream) {
+    return gcp_mttkrp_scaled(X, M, idx, ytilde, S, G, accumulate, nullptr, ws, ws_bytes, stream);
 }
 
 int64_t gcp_rejection_status_offset(const gcp_tensor* X, const gcp_factors* M, const gcp_sampling* cfg) {
@@ -618,6 +624,13 @@ gcp_status gcp_sampled_adam_step(gcp_loss loss, const gcp_tensor* X, const gcp_f
     }
     const AdamParams ap{A, A_master, B, C, state, alpha, beta1, beta2, adam_eps, lower, (int)eps_mode};
     return sampled_common(loss, X, M, cfg, eps, G, loss_sum, ws, ws_bytes, &ap, stream);
+}
+
+gcp_status gcp_bf16_round(int64_t P, const float* src, void* dst, hipStream_t stream) {
+    clear_error();
+    if (P < 0) return set_error(GCP_ERR_INVALID_ARG, "P must be >= 0");
+    if (P > 0 && (!src || !dst)) return set_error(GCP_ERR_INVALID_ARG, "src and dst must be non-NULL");
+    return launch_bf16_round(P, src, dst, stream);
 }
 
 gcp_status gcp_adam_step(int64_t P, gcp_dtype dtype, void* A, float* A_master, const void* G, void* B, void* C,

@@ -10,6 +10,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 #include "common.hpp"
 #include "device.hpp"
 
@@ -74,6 +76,19 @@ __global__ __launch_bounds__(256) void adam_kernel(AdamArgs a) {
             a.state[1] = 0;
         }
     }
+}
+
+__global__ __launch_bounds__(256) void bf16_round_kernel(int64_t P, const float* __restrict__ src,
+                                                           bf16_t* __restrict__ dst) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < P; e += (int64_t)gridDim.x * blockDim.x)
+        dst[e] = to_bf16(src[e]);
+}
+
+gcp_status launch_bf16_round(int64_t P, const float* src, void* dst, hipStream_t s) {
+    if (P <= 0) return GCP_OK;
+    const int64_t blocks = std::min<int64_t>((P + 255) / 256, 8192);
+    hipLaunchKernelGGL(bf16_round_kernel, dim3((unsigned)blocks), dim3(256), 0, s, P, src, static_cast<bf16_t*>(dst));
+    return check_launch("gcp_bf16_round");
 }
 
 gcp_status launch_adam(int64_t P, gcp_dtype dtype, void* A, float* A_master, const void* G, void* B, void* C,

@@ -200,7 +200,7 @@ gcp_status launch_grad_fused(gcp_loss loss, const gcp_tensor* X, const gcp_facto
 // A non-NULL bump_counter is incremented by the reduction (after every read).
 gcp_status launch_reduce(const gcp_factors* M, const ScatterPlan& pl, const double* acc,
                          const void* partials, void* const* G, int accumulate, const AdamParams* adam,
-                         uint64_t* bump_counter, hipStream_t s);
+                         uint64_t* bump_counter, hipStream_t s, const double* scale = nullptr);
 
 // Batched problems (batched.hip); check_problem validates one problem.
 gcp_status batch_create(const gcp_problem* problems, int32_t count, const gcp_batch_tuning* tune, gcp_batch** out,
@@ -217,6 +217,8 @@ int64_t batch_blocks(const gcp_batch* b);
 gcp_status batch_plan(const gcp_batch* b, int64_t* n_blocks, int64_t* n_units, int64_t* block_ptr,
                       int32_t* unit_problem, int64_t* unit_items);
 
+// dst[e] = src[e] rounded to bf16 (nearest even), e < P.
+gcp_status launch_bf16_round(int64_t P, const float* src, void* dst, hipStream_t s);
 gcp_status launch_adam(int64_t P, gcp_dtype dtype, void* A, float* A_master, const void* G,
                        void* B, void* C, int64_t* state, double alpha, double beta1, double beta2,
                        double eps, double lower, gcp_eps_mode eps_mode, hipStream_t s);

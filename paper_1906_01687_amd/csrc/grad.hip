@@ -53,6 +53,7 @@ struct ReduceArgs {
     int64_t off[GCP_MAX_D + 1];
     int64_t blk_start[GCP_MAX_D + 1];  // first workgroup of mode k; [d] = grid size
     uint64_t* bump_counter;
+    const double* scale;  // device scalar multiplying every gradient element (nullable)
     uint32_t priv_mask;
     int64_t lds_off[GCP_MAX_D];
     int64_t lds_total;
@@ -99,6 +100,7 @@ template <typename GT, int ADAM>
 __device__ __forceinline__ void finish_element(const ReduceArgs& a, int k, int64_t local, double g, double bc1d,
                                                double bc2d, bool have, GT pb, GT pc, GT pa, float pm) {
     const int64_t e = a.off[k] + local;
+    if (a.scale) g *= *a.scale;
     void* gk = a.G[0];
 #pragma unroll
     for (int q = 1; q < GCP_MAX_D; ++q)
@@ -540,9 +542,10 @@ gcp_status launch_grad_fused(gcp_loss loss, const gcp_tensor* X, const gcp_facto
 
 gcp_status launch_reduce(const gcp_factors* M, const ScatterPlan& pl, const double* acc, const void* partials,
                          void* const* G, int accumulate, const AdamParams* adam, uint64_t* bump_counter,
-                         hipStream_t s) {
+                         hipStream_t s, const double* scale) {
     ReduceArgs a{};
     a.bump_counter = bump_counter;
+    a.scale = scale;
     a.d = pl.d;
     a.P = pl.P;
     for (int k = 0; k <= GCP_MAX_D; ++k) a.off[k] = pl.off[k];

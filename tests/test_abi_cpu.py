@@ -397,3 +397,33 @@ def test_cols_per_lane_setter():
         assert L.gcp_set_cols_per_lane(bad) == 1
     for ok in (1, 2, 4, 0):
         assert L.gcp_set_cols_per_lane(ok) == 0
+
+
+def test_stratified_problems_are_refused_in_batches():
+    """Batches take uniform and semi-stratified sampling; a stratified problem
+    (rejection sampling of zeros, Alg. 2) is refused with GCP_ERR_UNSUPPORTED
+    and a message naming the problem, before any device work."""
+    m = _lib()
+    L = m.lib()
+    probs = (m.GcpProblem * 2)()
+    for b, sampler in enumerate((m.UNIFORM, m.STRATIFIED)):
+        pr = probs[b]
+        pr.X.d, pr.X.format, pr.X.vdtype = 3, m.COO, m.F32
+        for k, n in enumerate((20, 30, 40)):
+            pr.X.dims[k] = n
+        pr.X.nnz = 100
+        pr.X.coo_idx, pr.X.values, pr.X.nz_bitmap = 0x1000, 0x1000, 0x1000
+        pr.X.nz_table, pr.X.nz_slots = 0x1000, 256
+        pr.M.dtype, pr.M.rank = m.F32, 4
+        off = 0
+        for k, n in enumerate((20, 30, 40)):
+            pr.M.A[k] = 0x10000 + off * 4
+            off += n * 4
+        pr.cfg.sampler = sampler
+        pr.cfg.s, pr.cfg.p, pr.cfg.q = 500, 50, 50
+        pr.A, pr.B, pr.C = 0x10000, 0x20000, 0x30000
+        pr.lower = -math.inf
+    h = ctypes.c_void_p()
+    st = L.gcp_batched_create(probs, 2, None, ctypes.byref(h))
+    assert st == 2 and b"problem 1" in L.gcp_last_error() and b"SEMI_STRATIFIED" in L.gcp_last_error()
+    assert not h.value

@@ -72,6 +72,49 @@ def test_backward_scales_by_incoming_gradient():
     torch.testing.assert_close(p.grad, 3.0 * g1, rtol=1e-13, atol=0.0)
 
 
+def test_forward_on_a_copy_and_inplace_change():
+    """A forward on a tensor other than the Factors storage evaluates at that
+    tensor (its values are copied into the storage); changing the parameter
+    in place between forward and backward raises."""
+    announce("autograd: forward at a copy of the parameters, in-place change detected")
+    w = small_dense(dtype="f64", loss=synth.POISSON)
+    pb = to_device(w, dtype="f64")
+    sl = gcp.SampledLoss(w.loss, pb.X, pb.M, cfg_for(pb, iteration=1))
+    p = sl.parameter()
+    F0 = sl(p)
+    F0.backward()
+    g0 = p.grad.clone()
+    q = (p.detach() * 1.5).requires_grad_(True)
+    Fq = sl(q)
+    Fq.backward()
+    smp = oracle_samples(pb, iteration=1)
+    A15 = [1.5 * a for a in pb.A64]
+    Gq, Fqref = oracle.grad(w.loss, w.dims, A15, smp, s=w.s)
+    torch.cuda.synchronize()
+    assert abs(Fq.item() - Fqref) <= 1e-10 * max(1.0, abs(Fqref))
+    check_grad(pb.M.grad_views(q.grad), Gq, grad_scale(w.loss, w.dims, A15, smp, s=w.s), 1e-12, "autograd at a copy")
+    assert not torch.equal(q.grad, g0)
+    r = pb.M.flat.requires_grad_(True)
+    Fr = sl(r)
+    with torch.no_grad():
+        r.mul_(2.0)
+    with pytest.raises(RuntimeError):
+        Fr.backward()
+
+
+def test_bf16_shadow_refreshed_by_the_library():
+    announce("autograd BF16: the gather copy is the library's rounding of the parameter")
+    w = small_dense(dims=(11, 9, 7), rank=6, s=900)
+    pb = to_device(w, dtype="bf16")
+    sl = gcp.SampledLoss(w.loss, pb.X, pb.M, cfg_for(pb, iteration=2))
+    p = sl.parameter()
+    with torch.no_grad():
+        p.add_(torch.randn_like(p) * 1e-2)
+    sl(p).backward()
+    torch.cuda.synchronize()
+    assert torch.equal(pb.M.flat, p.detach().to(torch.bfloat16))
+
+
 def _oracle_loss(pb, smp, A):
     _, F = oracle.grad(pb.w.loss, pb.w.dims, A, smp, nnz=pb.w.nnz, s=pb.w.s, p=pb.w.p, q=pb.w.q)
     return F
