@@ -19,6 +19,8 @@ __device__ __forceinline__ uint64_t chunk_prefix(const GradArgs& a, int64_t chun
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t g = chunk / (kRejThreads / kWave);
     uint64_t s = 0;
+    // up to 8 loads per lane in flight before they are summed
+#pragma unroll 8
     for (int64_t b = lane; b < g; b += kWave) s += a.group_sum[b];
     if (lane < chunk - g * (kRejThreads / kWave)) s += a.chunk_count[g * (kRejThreads / kWave) + lane];
     return wave_sum_u64(s);
@@ -60,15 +62,16 @@ __device__ __forceinline__ Sample<D, typename Compute<FT>::type> item_sample(con
     } else if constexpr (!LIST) {
         // stratified zeros: the accepted candidates of one 64-candidate chunk,
         // staged in counter order by the count kernel
+        // the staged indices and the chunk's count do not depend on the
+        // prefix, so their loads go out together with the prefix's (a slot
+        // past the count holds stale data and is dropped below)
         const int64_t chunk = item - a.n_direct_items;
-        const uint64_t rank = chunk_prefix(a, chunk) + (uint64_t)lane;
-        const uint32_t cnt = a.chunk_count[chunk];
-        if ((uint32_t)lane < cnt && rank < (uint64_t)a.q) {
-            uint32_t i[D];
+        uint32_t i[D];
 #pragma unroll
-            for (int k = 0; k < D; ++k) i[k] = a.zstage[((int64_t)chunk * kWave + lane) * D + k];
-            smp = make_sample<D, T>(a, i, T(0), GCP_STRATUM_ZERO);
-        }
+        for (int k = 0; k < D; ++k) i[k] = a.zstage[((int64_t)chunk * kWave + lane) * D + k];
+        const uint32_t cnt = a.chunk_count[chunk];
+        const uint64_t rank = chunk_prefix(a, chunk) + (uint64_t)lane;
+        if ((uint32_t)lane < cnt && rank < (uint64_t)a.q) smp = make_sample<D, T>(a, i, T(0), GCP_STRATUM_ZERO);
     }
     return smp;
 }
@@ -87,19 +90,29 @@ __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
     // nothing in this kernel reads the step count; the reduction after it does
     if (a.adam_state && blockIdx.x == 0 && threadIdx.x == 0) a.adam_state[0] += 1;
 
-    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+    const int64_t wave = uni((int64_t)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave));
     const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) / kWave;
     const int64_t n_items = a.n_direct_items + a.n_zero_items;
     const uint64_t iter = effective_iteration(a.iter, a.iter_ctr);
     T fsum = T(0);
     const uint64_t stride = a.item_stride;
+    const double inv_items = 1.0 / (double)(n_items > 0 ? n_items : 1);
     auto item_at = [&](int64_t g) -> int64_t {
-        return stride > 1 ? (int64_t)(((uint64_t)g * stride) % (uint64_t)n_items) : g;
+        if (stride <= 1) return g;
+        // (g * stride) mod n without a 64-bit division: g, stride < n < 2^32,
+        // so the quotient estimate from the double reciprocal is off by at
+        // most 2 and the remainder is corrected into [0, n)
+        const uint64_t p = (uint64_t)g * stride;
+        const uint64_t q = (uint64_t)((double)p * inv_items);
+        int64_t r = (int64_t)(p - q * (uint64_t)n_items);
+        while (r < 0) r += n_items;
+        while (r >= n_items) r -= n_items;
+        return r;
     };
 
-    // the first item's draws and gathers are issued before the LDS clear, so
-    // the clear runs under their latency
-    Sample<D, T> cur = wave < n_items ? item_sample<D, FT, VT, LIST>(a, iter, item_at(wave)) : no_sample<D, T>();
+    // clear the LDS partial first: after this one barrier every wave runs
+    // its draws, gathers and scatter at its own pace (a barrier after the
+    // draws would hold each wave back to its workgroup's slowest draw)
     {
         constexpr int per16 = 16 / sizeof(LT);
         uint4* l16 = reinterpret_cast<uint4*>(lds_raw);
@@ -108,6 +121,7 @@ __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
         for (int64_t e = n16 * per16 + threadIdx.x; e < a.lds_total; e += nthreads) lds[e] = LT(0);
     }
     __syncthreads();
+    Sample<D, T> cur = wave < n_items ? item_sample<D, FT, VT, LIST>(a, iter, item_at(wave)) : no_sample<D, T>();
 
     for (int64_t g = wave; g < n_items; g += nwave) {
         const int64_t item = item_at(g);
@@ -164,10 +178,16 @@ __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
                 v[0] = (LT)u.x, v[1] = (LT)u.y, v[2] = (LT)u.z, v[3] = (LT)u.w;
             }
             if constexpr (sizeof(PT) == 4) {
-                reinterpret_cast<float4*>(part)[e] = float4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+                // streamed past the L2: the reduction runs on every XCD, so a
+                // partial cached in this XCD's L2 would only have to be
+                // written back when the kernel ends
+                using f32x4 = float __attribute__((ext_vector_type(4)));
+                __builtin_nontemporal_store(f32x4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]},
+                                            reinterpret_cast<f32x4*>(part) + e);
             } else {
-                reinterpret_cast<double2*>(part)[2 * e] = double2{(double)v[0], (double)v[1]};
-                reinterpret_cast<double2*>(part)[2 * e + 1] = double2{(double)v[2], (double)v[3]};
+                using f64x2 = double __attribute__((ext_vector_type(2)));
+                __builtin_nontemporal_store(f64x2{(double)v[0], (double)v[1]}, reinterpret_cast<f64x2*>(part) + 2 * e);
+                __builtin_nontemporal_store(f64x2{(double)v[2], (double)v[3]}, reinterpret_cast<f64x2*>(part) + 2 * e + 1);
             }
         }
     } else {
