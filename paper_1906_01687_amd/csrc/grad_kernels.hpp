@@ -93,7 +93,6 @@ __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
     const int64_t wave = uni((int64_t)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave));
     const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) / kWave;
     const int64_t n_items = a.n_direct_items + a.n_zero_items;
-    const uint64_t iter = effective_iteration(a.iter, a.iter_ctr);
     T fsum = T(0);
     const uint64_t stride = a.item_stride;
     const double inv_items = 1.0 / (double)(n_items > 0 ? n_items : 1);
@@ -121,6 +120,9 @@ __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
         for (int64_t e = n16 * per16 + threadIdx.x; e < a.lds_total; e += nthreads) lds[e] = LT(0);
     }
     __syncthreads();
+    // the device iteration counter is read only now, so its load does not
+    // hold up the clear
+    const uint64_t iter = effective_iteration(a.iter, a.iter_ctr);
     Sample<D, T> cur = wave < n_items ? item_sample<D, FT, VT, LIST>(a, iter, item_at(wave)) : no_sample<D, T>();
 
     for (int64_t g = wave; g < n_items; g += nwave) {
