@@ -102,6 +102,10 @@ BATCH_KERNEL_SOURCES = [_CSRC + f for f in ("batched_kernels.hpp", "batched.hip"
 # per CU per cycle.  In G wave-instructions per second.
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4 / 1e9
 LDS_ISSUE_PEAK = 256 * 2.4e9 / 1e9
+# LDS FP64 atomic adds: a 64-lane ds_add_f64 with the scatter's address
+# pattern occupies a CU's LDS for about 24 cycles (measured on MI355X), so
+# 256 CUs add at most 256 * 64 / 24 * 2.4e9 elements per second (G adds/s).
+LDS_ATOMIC_PEAK = 256 * 64 / 24 * 2.4e9 / 1e9
 
 
 def kernel_source_hash(read=None, sources=None) -> str:
@@ -140,17 +144,23 @@ def profiled(name: str, sources):
     return fields
 
 
-def issue_rates(fields, kernel_us: float):
-    """VALU and LDS wave-instruction rates of a kernel (counts per launch from
-    its profile over the live kernel duration) against the issue peaks."""
-    if not fields or "sq_insts_valu_per_launch" not in fields:
-        return None
-    valu = float(fields["sq_insts_valu_per_launch"]) / (kernel_us * 1e-6) / 1e9
-    lds = float(fields["sq_insts_lds_per_launch"]) / (kernel_us * 1e-6) / 1e9
-    return {"unit": "G wave-instructions/s",
-            "valu": {"achieved": valu, "peak": VALU_ISSUE_PEAK, "frac": valu / VALU_ISSUE_PEAK},
-            "lds": {"achieved": lds, "peak": LDS_ISSUE_PEAK, "frac": lds / LDS_ISSUE_PEAK},
-            "source": "SQ_INSTS_VALU, SQ_INSTS_LDS per launch (rocprofv3 --pmc, profiles/)"}
+def issue_rates(fields, kernel_us: float, scatter_adds: float):
+    """The kernel against the on-chip resources that bind it: its MTTKRP
+    scatter's element adds per second (sum over samples of d r, from the
+    workload) against the LDS FP64 atomic rate, and its VALU and LDS
+    wave-instruction rates (counts per launch from its profile, over the live
+    kernel duration) against the issue peaks."""
+    adds = scatter_adds / (kernel_us * 1e-6) / 1e9
+    out = {"scatter_adds": {"achieved": adds, "peak": LDS_ATOMIC_PEAK, "frac": adds / LDS_ATOMIC_PEAK,
+                            "unit": "G element adds/s", "per_launch": scatter_adds}}
+    if fields and "sq_insts_valu_per_launch" in fields:
+        valu = float(fields["sq_insts_valu_per_launch"]) / (kernel_us * 1e-6) / 1e9
+        lds = float(fields["sq_insts_lds_per_launch"]) / (kernel_us * 1e-6) / 1e9
+        out.update({"unit": "G wave-instructions/s",
+                    "valu": {"achieved": valu, "peak": VALU_ISSUE_PEAK, "frac": valu / VALU_ISSUE_PEAK},
+                    "lds": {"achieved": lds, "peak": LDS_ISSUE_PEAK, "frac": lds / LDS_ISSUE_PEAK},
+                    "source": "SQ_INSTS_VALU, SQ_INSTS_LDS per launch (rocprofv3 --pmc, profiles/)"})
+    return out
 
 
 def usable_cores(limit: int = 16) -> int:
@@ -355,7 +365,7 @@ def run_batched(args, ws, cpu):
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "batched_grad_kernel (64 problems: draws + model + derivative + MTTKRP scatter)",
                      "kernel_us": kernel_ms * 1e3, "algorithmic_bytes_per_launch": balg},
-        "issue": issue_rates(prof, kernel_ms * 1e3),
+        "issue": issue_rates(prof, kernel_ms * 1e3, sum(w.s * 3 * w.rank for w in ws)),
         "batched_launch": "2 kernels per step (gradient, reduction + Adam); K steps replayed as one "
                           "library-owned HIP graph (gcp_batched_graph_capture / _launch)",
         "plain_per_problem": {"ms_per_step": plain_ms, "value": samples / (plain_ms / 1e3),
@@ -495,7 +505,7 @@ def main():
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "grad_kernel (fused draws + model + derivative + MTTKRP scatter)",
                      "kernel_us": kernel_ms * 1e3, "algorithmic_bytes_per_launch": balg},
-        "issue": issue_rates(prof, kernel_ms * 1e3),
+        "issue": issue_rates(prof, kernel_ms * 1e3, float(samples) * w.d * w.rank),
         "cpu_baseline": cpu,
     }
     if autograd is not None:

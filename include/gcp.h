@@ -223,7 +223,8 @@ gcp_status gcp_set_cols_per_lane(int32_t cpl);
  * plus eight standard deviations of the candidate count (App. B) is refused
  * with GCP_ERR_UNSUPPORTED, so the cap is reached with probability below
  * 1e-15.  If it is reached, the rejection status word reads 1 (see
- * gcp_rejection_status_offset) and the unfilled zero slots hold no samples. */
+ * gcp_rejection_status_offset): gcp_sample leaves the zero slots past the
+ * last one drawn unwritten, and the fused calls use the zeros drawn so far. */
 size_t gcp_sample_workspace_bytes(const gcp_tensor *X, const gcp_sampling *cfg);
 gcp_status gcp_sample(const gcp_tensor *X, const gcp_sampling *cfg,
                       uint32_t *idx, void *xval, uint8_t *stratum,
