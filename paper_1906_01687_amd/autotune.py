@@ -28,7 +28,8 @@ from .api import Batch, Problem
 
 DEFAULT_CANDIDATES: Tuple[Tuple[int, int, int, int], ...] = tuple(
     [(t, 0, _lib.BATCH_CONTIGUOUS, c) for t in (512, 1024) for c in (0, 1, 2, 4)]
-    + [(t, u, _lib.BATCH_LPT, c) for t in (256, 512, 1024) for u in (16, 64, 256) for c in (0, 1, 2, 4)])
+    + [(t, u, _lib.BATCH_LPT, c) for t in (256, 512, 1024) for u in (16, 64, 256) for c in (0, 1, 2, 4)]
+    + [(1024, u, _lib.BATCH_LPT, c) for u in (32, 128) for c in (0, 1, 2, 4)])
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "gcp_mi355x", "batch_tuning.json")
 
 
