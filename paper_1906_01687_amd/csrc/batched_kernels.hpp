@@ -35,7 +35,8 @@ __global__ __launch_bounds__(1024) void batched_grad_kernel(BatchGradArgs ba) {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t wib = threadIdx.x / kWave;
     const int64_t nwib = blockDim.x / kWave;
-    const uint64_t ctr = ba.iter_ctr ? *ba.iter_ctr : 0;
+    // in flight across the first LDS clear and its barrier
+    const uint64_t ctr = ba.iter_ctr ? counter_vmem(ba.iter_ctr) : 0;
     T fsum = T(0);
     const int64_t u_end = ba.block_ptr[blockIdx.x + 1];
     int32_t prev = -1;
@@ -51,7 +52,7 @@ __global__ __launch_bounds__(1024) void batched_grad_kernel(BatchGradArgs ba) {
             else clear_lds(lds, n);
             __syncthreads();
         }
-        const uint64_t iter = a.iter + ctr;
+        const uint64_t iter = a.iter + (uint64_t)uni((int64_t)ctr);
         auto draw = [&](int64_t item) {
             const int64_t c = item * kWave + lane;
             Sample<D, T> smp = no_sample<D, T>();

@@ -92,6 +92,10 @@ int cols_per_lane(int64_t r, int hint, bool device_atomics = false);
 int lanes_per_sample(int64_t r, int cpl);
 // Whether cpl columns per lane can carry rank r (every sample fits one wave).
 bool cols_per_lane_fits(int64_t r, int cpl);
+// Swizzle of the single-problem kernel's LDS partial (d modes, elements of
+// elem_bytes, rows of r columns handled as cpl chunks of lps): shift and mask
+// of lds_swizzle, mask 0 for the plain layout.
+void lds_swizzle_params(int d, int64_t r, int lps, int cpl, int elem_bytes, uint32_t* shift, uint32_t* mask);
 extern std::atomic<int> g_cols_per_lane;
 
 // Multiprocessor count of the current device (cached per device).

@@ -315,6 +315,31 @@ int cols_per_lane(int64_t r, int hint, bool device_atomics) {
     return 4;
 }
 
+void lds_swizzle_params(int d, int64_t r, int lps, int cpl, int elem_bytes, uint32_t* shift, uint32_t* mask) {
+    *shift = 0;
+    *mask = 0;
+    // In one column step the 64 / lps samples of a wave add into chunk c of
+    // their rows; with rows of at most 256 bytes (64 LDS banks) the row's
+    // place in a 256-byte window spreads them over only 256 / (r * 8)
+    // positions.  Flipping the chunk index by the row bits just above those
+    // that fix that place spreads them over 256 / (lps * 8).  Measured on
+    // MI355X with this pattern: FP64 adds at r = 8, 16, 32 take about a fifth
+    // fewer cycles per instruction; the FP32 compare-and-swap adds gain a few
+    // percent, so only FP64 partials are swizzled.  Chunks of at least 32
+    // bytes (lps >= 4) keep the 32-byte reads of the partial's flush whole.
+    if (elem_bytes != 8 || cpl < 2 || lps < 4 || r != (int64_t)cpl * lps || r * 8 > 256 || d > 3) return;
+    auto lg = [](int64_t v) {
+        int l = 0;
+        while ((int64_t{1} << l) < v) ++l;
+        return l;
+    };
+    const int chunk_bit = lg((int64_t)lps * 8);  // lowest bit of the chunk index
+    const int row_bit = lg(r * 8);               // lowest bit of the row index
+    const int window_bit = row_bit > 8 ? row_bit : 8;
+    *shift = (uint32_t)(window_bit - chunk_bit);
+    *mask = (uint32_t)(cpl - 1) << chunk_bit;
+}
+
 int lanes_per_sample(int64_t r, int cpl) {
     const int64_t need = (r + cpl - 1) / cpl;
     int l = 1;
@@ -445,6 +470,7 @@ static GradArgs base_args(const gcp_tensor* X, const gcp_factors* M, const Scatt
     a.r = (int)M->rank;
     a.cpl = cols_per_lane(M->rank, 0, pl.priv_mask != (1u << X->d) - 1u);
     a.lps = lanes_per_sample(M->rank, a.cpl);
+    lds_swizzle_params(X->d, M->rank, a.lps, a.cpl, pl.lds_elem, &a.lds_swz_shift, &a.lds_swz_mask);
     a.nnz = X->nnz;
     a.values = X->values;
     a.coo = X->coo_idx;

@@ -44,6 +44,10 @@ struct GradArgs {
     uint32_t priv_mask;
     int64_t lds_off[GCP_MAX_D];
     int64_t lds_total;
+    // FP64 LDS partial of the single-problem kernel only: the element at
+    // byte offset o (row-major order from the partial's start) is kept at
+    // lds_swizzle(o, lds_swz_shift, lds_swz_mask); mask 0 is the plain layout
+    uint32_t lds_swz_shift, lds_swz_mask;
     void* partials;  // [gridDim.x][lds_total], FP64 for FP64 factors, else FP32
     // device accumulator of the modes not privatised: FP64, or FP32 when
     // acc32; row i of mode k starts at element acc_off[k] + i * acc_stride,
@@ -69,6 +73,14 @@ struct GradArgs {
 };
 
 constexpr uint32_t kNoStage = 0xFFFFFFFFu;
+
+// XOR swizzle of an LDS partial's byte offsets: the chunk bits selected by
+// mask are flipped by the row bits `shift` places above them.  Those row bits
+// lie above every bit the mask selects, so the map is its own inverse and
+// keeps each element in its row.
+__device__ __forceinline__ uint32_t lds_swizzle(uint32_t o, uint32_t shift, uint32_t mask) {
+    return o ^ ((o >> shift) & mask);
+}
 
 
 // Partial-gradient storage: FP64 for FP64 factors, FP32 otherwise.
@@ -329,6 +341,15 @@ template <> struct RowLoad<bf16_t> {
 
 constexpr int kBufferWord3 = 0x00020000;  // raw buffer, 32-bit elements, gfx9 family
 
+// The iteration counter through a buffer load, which is a vector-memory load:
+// it stays in flight across a barrier that waits only for LDS operations.
+__device__ __forceinline__ uint64_t counter_vmem(const uint64_t* p) {
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint64_t*>(p), (short)0, 8, kBufferWord3);
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, 0u, 0, 0);
+    return ((uint64_t)v[1] << 32) | v[0];
+}
+
 // Values that are the same on every lane but that the compiler cannot prove
 // uniform (fields of an argument block read from global memory) are moved to
 // scalar registers, so buffer descriptors and branches built from them stay
@@ -355,6 +376,7 @@ template <int D, typename LT>
 struct PhaseB {
     int lps, spw, slot, r, loss;
     uint32_t j, cmask, priv;
+    uint32_t swz_shift, swz_mask;
     double kz;
     __amdgpu_buffer_rsrc_t rs[D];
     uint32_t lbase[D];
@@ -379,7 +401,7 @@ constexpr int passes_per_batch() {
     return nb < cap ? nb : cap;
 }
 
-template <int NB, int CPL, int D, typename FT, bool LIST, typename LT, bool STAGED>
+template <int NB, int CPL, int D, typename FT, bool LIST, typename LT, bool STAGED, bool SWZ>
 __device__ __forceinline__ void pass_batches(const GradArgs& a, const PhaseB<D, LT>& b, LT* __restrict__ lds,
                                              const Sample<D, typename Compute<FT>::type>* stage,
                                              const Sample<D, typename Compute<FT>::type>& smp,
@@ -450,14 +472,18 @@ __device__ __forceinline__ void pass_batches(const GradArgs& a, const PhaseB<D, 
                 for (int k = 0; k < D; ++k) {
                     uint32_t row = qq[u][k];
                     if (!((b.priv >> k) & 1u) && b.acc_magic) row = __umulhi(row, b.acc_magic) * b.acc_stride;
+                    // byte offset of the lane's first column in the LDS
+                    // partial, and the row's swizzle of the chunk bits
+                    const uint32_t lrow = b.lbase[k] + qq[u][k] * (uint32_t)sizeof(LT);
+                    const uint32_t hs = SWZ ? (lrow >> b.swz_shift) & b.swz_mask : 0u;
 #pragma unroll
                     for (int c = 0; c < CPL; ++c) {
                         if (!((b.cmask >> c) & 1u)) continue;
                         const T v = y * (pre[k][c] * suf[k][c]);
                         const uint32_t cc = (uint32_t)(c * b.lps);
                         if ((b.priv >> k) & 1u)
-                            lds_add(reinterpret_cast<LT*>(reinterpret_cast<char*>(lds) + b.lbase[k] +
-                                                          (qq[u][k] + cc) * (uint32_t)sizeof(LT)),
+                            lds_add(reinterpret_cast<LT*>(reinterpret_cast<char*>(lds) +
+                                                          ((lrow + cc * (uint32_t)sizeof(LT)) ^ hs)),
                                     (LT)v);
                         else if (b.acc32)
                             unsafeAtomicAdd(static_cast<float*>(b.accj[k]) + (row + cc), (float)v);
@@ -470,7 +496,7 @@ __device__ __forceinline__ void pass_batches(const GradArgs& a, const PhaseB<D, 
     }
 }
 
-template <int CPL, int D, typename FT, bool LIST, typename LT, bool STAGED>
+template <int CPL, int D, typename FT, bool LIST, typename LT, bool STAGED, bool SWZ = false>
 __device__ __forceinline__ void run_passes(const GradArgs& a, const PhaseB<D, LT>& b, LT* __restrict__ lds,
                                            const Sample<D, typename Compute<FT>::type>* stage,
                                            const Sample<D, typename Compute<FT>::type>& smp,
@@ -479,10 +505,10 @@ __device__ __forceinline__ void run_passes(const GradArgs& a, const PhaseB<D, LT
     constexpr int nb = passes_per_batch<D, T, CPL>();
     if constexpr (CPL == 1 && nb == 8) {
         // lane groups of at most 4 lanes have at most 4 passes per item
-        if (b.lps <= 4) pass_batches<4, 1, D, FT, LIST, LT, STAGED>(a, b, lds, stage, smp, fsum);
-        else pass_batches<8, 1, D, FT, LIST, LT, STAGED>(a, b, lds, stage, smp, fsum);
+        if (b.lps <= 4) pass_batches<4, 1, D, FT, LIST, LT, STAGED, SWZ>(a, b, lds, stage, smp, fsum);
+        else pass_batches<8, 1, D, FT, LIST, LT, STAGED, SWZ>(a, b, lds, stage, smp, fsum);
     } else {
-        pass_batches<nb, CPL, D, FT, LIST, LT, STAGED>(a, b, lds, stage, smp, fsum);
+        pass_batches<nb, CPL, D, FT, LIST, LT, STAGED, SWZ>(a, b, lds, stage, smp, fsum);
     }
 }
 
@@ -496,10 +522,12 @@ __device__ __forceinline__ void run_passes(const GradArgs& a, const PhaseB<D, LT
 // of its rows, so one pass covers 64/lps samples; the model entry's column
 // sum is taken over the lane's columns, then over the group.  Passes are taken 1 to 8 at a time so that the row gathers of a batch
 // are all in flight before any of them is consumed.  Every lane of the wave
-// must call this.  PADDED_ACC = false fixes the device accumulator to FP64
-// rows of r (the batched kernel's layout), so none of the padded-row code is
-// generated.
-template <int D, typename FT, bool LIST, typename LT = double, bool PADDED_ACC = true>
+// must call this.  SINGLE = false (the batched kernel) fixes the device
+// accumulator to FP64 rows of r and the LDS partial to the plain layout, so
+// neither the padded-row nor the swizzle arithmetic is generated (in the
+// batched kernel, measured on MI355X, the swizzle's address arithmetic cost
+// more than its LDS adds gained).
+template <int D, typename FT, bool LIST, typename LT = double, bool SINGLE = true>
 __device__ __forceinline__ void evaluate_and_scatter(const GradArgs& a, LT* __restrict__ lds,
                                                      Sample<D, typename Compute<FT>::type>* stage,
                                                      const Sample<D, typename Compute<FT>::type>& smp,
@@ -519,11 +547,15 @@ __device__ __forceinline__ void evaluate_and_scatter(const GradArgs& a, LT* __re
     b.priv = uni(a.priv_mask);
     b.kz = a.kz;
     char* const acc = reinterpret_cast<char*>(uni(a.acc));
-    if constexpr (PADDED_ACC) {
+    if constexpr (SINGLE) {
+        b.swz_shift = uni(a.lds_swz_shift);
+        b.swz_mask = uni(a.lds_swz_mask);
         b.acc32 = uni(a.acc32) != 0;
         b.acc_stride = uni(a.acc_stride);
         b.acc_magic = uni(a.acc_magic);
     } else {
+        b.swz_shift = 0;
+        b.swz_mask = 0;
         b.acc32 = false;
         b.acc_stride = 0;
         b.acc_magic = 0;
@@ -538,17 +570,27 @@ __device__ __forceinline__ void evaluate_and_scatter(const GradArgs& a, LT* __re
         b.lbase[k] = (uint32_t)((uni(a.lds_off[k]) + (int64_t)b.j) * (int64_t)sizeof(LT));
         b.accj[k] = acc ? acc + (uni(a.acc_off[k]) + (int64_t)b.j) * acc_elem : nullptr;
     }
+    // the swizzle (cpl >= 2 and an FP64 partial only) is a separate code
+    // path, so launches without it carry none of its address arithmetic; it
+    // is compiled for d <= 3 only (at d = 4 its extra path pushed the kernel
+    // into register spills that cost more than it gained)
+    constexpr bool can_swz = SINGLE && sizeof(LT) == 8 && D <= 3;
+    const bool swz = can_swz && b.swz_mask != 0;
     if (uni(a.stage_off) != kNoStage) {
         // the wave's own slice: ds operations of one wave complete in order, so
         // the reads below see these writes and the next item's writes cannot
         // overtake them
         stage[lane] = smp;
         if (cpl == 1) run_passes<1, D, FT, LIST, LT, true>(a, b, lds, stage, smp, fsum);
+        else if (cpl == 2 && swz) run_passes<2, D, FT, LIST, LT, true, can_swz>(a, b, lds, stage, smp, fsum);
         else if (cpl == 2) run_passes<2, D, FT, LIST, LT, true>(a, b, lds, stage, smp, fsum);
+        else if (swz) run_passes<4, D, FT, LIST, LT, true, can_swz>(a, b, lds, stage, smp, fsum);
         else run_passes<4, D, FT, LIST, LT, true>(a, b, lds, stage, smp, fsum);
     } else {
         if (cpl == 1) run_passes<1, D, FT, LIST, LT, false>(a, b, lds, stage, smp, fsum);
+        else if (cpl == 2 && swz) run_passes<2, D, FT, LIST, LT, false, can_swz>(a, b, lds, stage, smp, fsum);
         else if (cpl == 2) run_passes<2, D, FT, LIST, LT, false>(a, b, lds, stage, smp, fsum);
+        else if (swz) run_passes<4, D, FT, LIST, LT, false, can_swz>(a, b, lds, stage, smp, fsum);
         else run_passes<4, D, FT, LIST, LT, false>(a, b, lds, stage, smp, fsum);
     }
 }

@@ -109,6 +109,9 @@ __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
         return r;
     };
 
+    // the device iteration counter is loaded first and used after the
+    // barrier below, so its latency overlaps the LDS clear
+    const uint64_t ctr = a.iter_ctr ? counter_vmem(a.iter_ctr) : 0;
     // clear the LDS partial first: after this one barrier every wave runs
     // its draws, gathers and scatter at its own pace (a barrier after the
     // draws would hold each wave back to its workgroup's slowest draw)
@@ -120,9 +123,7 @@ __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
         for (int64_t e = n16 * per16 + threadIdx.x; e < a.lds_total; e += nthreads) lds[e] = LT(0);
     }
     __syncthreads();
-    // the device iteration counter is read only now, so its load does not
-    // hold up the clear
-    const uint64_t iter = effective_iteration(a.iter, a.iter_ctr);
+    const uint64_t iter = a.iter + (uint64_t)uni((int64_t)ctr);
     Sample<D, T> cur = wave < n_items ? item_sample<D, FT, VT, LIST>(a, iter, item_at(wave)) : no_sample<D, T>();
 
     for (int64_t g = wave; g < n_items; g += nwave) {
@@ -172,8 +173,10 @@ __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
         for (int64_t e = threadIdx.x; e < a.lds_total / 4; e += nthreads) {
             LT v[4];
             if constexpr (sizeof(LT) == 8) {
-                const double2 u = reinterpret_cast<const double2*>(lds_raw)[2 * e];
-                const double2 w = reinterpret_cast<const double2*>(lds_raw)[2 * e + 1];
+                // four elements are 32 bytes, inside one chunk of the swizzle
+                const uint32_t o = lds_swizzle((uint32_t)e * 32u, a.lds_swz_shift, a.lds_swz_mask);
+                const double2 u = *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(lds_raw) + o);
+                const double2 w = *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(lds_raw) + o + 16);
                 v[0] = (LT)u.x, v[1] = (LT)u.y, v[2] = (LT)w.x, v[3] = (LT)w.y;
             } else {
                 const float4 u = reinterpret_cast<const float4*>(lds_raw)[e];
@@ -193,7 +196,11 @@ __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
             }
         }
     } else {
-        for (int64_t e = threadIdx.x; e < a.lds_total; e += nthreads) part[e] = (PT)lds[e];
+        for (int64_t e = threadIdx.x; e < a.lds_total; e += nthreads) {
+            const uint32_t o = sizeof(LT) == 8 ? lds_swizzle((uint32_t)e * 8u, a.lds_swz_shift, a.lds_swz_mask)
+                                               : (uint32_t)e * (uint32_t)sizeof(LT);
+            part[e] = (PT) * reinterpret_cast<const LT*>(reinterpret_cast<const char*>(lds_raw) + o);
+        }
     }
 }
 
