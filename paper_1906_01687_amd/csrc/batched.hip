@@ -33,6 +33,9 @@
 
 namespace gcp {
 
+// The fixed per-sample cost of the batch planner's estimate, in scattered elements.
+constexpr int64_t kSampleFixedCost = 19;
+
 // What the reduction needs per problem.
 struct BatchReduceProblem {
     int64_t flat_off;  // first element of the problem in the concatenated accumulator
@@ -263,8 +266,11 @@ gcp_status batch_create(const gcp_problem* problems, int32_t count, const gcp_ba
         rp.lower = pr.lower;
         B->red[b] = rp;
         flat += P;
-        // estimated cost of one sample: the scatter of its d rows of r entries
-        item_cost[b] = (double)kWave * (double)(d * std::max<int64_t>(r, 4));
+        // estimated cost of one sample in units of one scattered element: a
+        // fixed part (draw, gather, derivative, group sum) and the scatter of
+        // its d rows of r entries (fitted to sub-batches of 64 dense cubes by
+        // rank on MI355X: about 52, 97 and 194 ps per sample at r = 4, 16, 32)
+        item_cost[b] = (double)kWave * (double)(kSampleFixedCost + d * r);
         items[b] = a.n_direct_items;
         total_items += a.n_direct_items;
     }
@@ -316,7 +322,11 @@ gcp_status batch_create(const gcp_problem* problems, int32_t count, const gcp_ba
                 costs.push_back({item_cost[b] * (double)(i1 - i0), BatchUnit{b, 0, i0, i1}});
             }
         // longest processing time first onto the least-loaded workgroup, then
-        // each workgroup's units in problem order so it flushes once per problem
+        // each workgroup's units in problem order so it flushes once per
+        // problem.  (Dealing each XCD's share of the problem-ordered units over
+        // that XCD's workgroups only, for L2 locality, was measured slower on
+        // 64 dense cubes, 202 against 195 us: with few problems per workgroup
+        // the errors of the cost estimate no longer average out.)
         std::stable_sort(costs.begin(), costs.end(), [](const Cost& x, const Cost& y) { return x.cost > y.cost; });
         using Slot = std::pair<double, int64_t>;
         std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> heap;
