@@ -458,7 +458,13 @@ def main():
         stop.record()
         torch.cuda.synchronize()
         total_ms = start.elapsed_time(stop)
-        # the gradient kernel's own duration: event pairs around it in K eager steps
+        # the gradient kernel's own duration: event pairs around it in K eager
+        # steps, after K untimed eager steps (the first eager block of a
+        # process issues slower, and its events then read about 1.5 us more
+        # per launch than every later block)
+        for it in range(args.steps):
+            step_call()
+        torch.cuda.synchronize()
         _lib.check(L.gcp_timing_start(args.steps))
         for it in range(args.steps):
             step_call()

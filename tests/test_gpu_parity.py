@@ -142,6 +142,9 @@ CASES = [
     ("dense_f32_r16_swizzled", lambda: small_dense(rank=16, loss=synth.POISSON)),
     ("dense_f32_r32_swizzled", lambda: small_dense(rank=32)),
     ("dense_f64_r8_swizzled", lambda: small_dense(rank=8, dtype="f64", loss=synth.BERNOULLI_ODDS)),
+    # ranks 3 and 4: lane pairs at two columns per lane, a lane per sample at four
+    ("dense_f32_r4", lambda: small_dense(rank=4, loss=synth.POISSON)),
+    ("counts_strat_r3", lambda: small_sparse("counts", rank=3, sampler=synth.STRATIFIED)),
     ("binary_strat_r7", lambda: small_sparse("binary")),
     ("binary_semi_r8", lambda: small_sparse("binary", rank=8, sampler=synth.SEMI_STRATIFIED)),
     ("counts_semi_r10", lambda: small_sparse("counts", rank=10)),
@@ -387,7 +390,7 @@ VARIANT_CASES = [c for c in CASES if c[0] in (
     "dense_f32_r5", "binary_strat_r7", "binary_semi_r8", "counts_semi_r10", "counts_strat_r33", "dense_f32_d5_r16",
     "dense_f64_d2_r2", "counts_semi_fp32_lds", "dense_bf16_r64_fp32_lds", "counts_semi_long_mode_r10",
     "dense_f64_long_mode_r5", "counts_strat_gamma_r5", "dense_f32_r16_swizzled", "dense_f32_r32_swizzled",
-    "dense_f64_r8_swizzled")]
+    "dense_f64_r8_swizzled", "dense_f32_r4", "counts_strat_r3")]
 
 
 @pytest.mark.parametrize("cpl", [1, 2, 4])
