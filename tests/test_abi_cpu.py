@@ -337,6 +337,26 @@ def test_profile_hash_ignores_comments_only():
     assert bench.kernel_source_hash(lambda rel: changed[rel]) != h0
 
 
+def test_roofline_is_a_ceiling():
+    """bench.py's roofline is the byte model against HBM while its fraction is
+    at most 1, else the tightest on-chip ceiling (LDS atomic adds or VALU
+    issue), with the byte model kept beside it; no roofline fraction exceeds 1."""
+    import bench
+    fields = {"sq_insts_valu_per_launch": "6.0e7", "sq_insts_lds_per_launch": "3.0e6"}
+    issue = bench.issue_rates(fields, 200.0, 1.3e8)
+    hbm = {"bound": "hbm", "achieved": 8200.0, "peak": bench.HBM_PEAK_GBS, "unit": "GB/s", "frac": 8200.0 / 8000.0,
+           "traffic": 4.9e8, "traffic_unit": "bytes", "kernel": "k", "kernel_us": 200.0,
+           "algorithmic_bytes_per_launch": 1.6e9}
+    r = bench.roofline_of(hbm, issue)
+    assert r["bound"] == "alu" and r["frac"] <= 1.0
+    assert r["frac"] == max(issue["scatter_adds"]["frac"], issue["valu"]["frac"])
+    assert r["hbm_byte_model"]["frac"] == hbm["frac"] and r["traffic"] == hbm["traffic"]
+    low = dict(hbm, achieved=3000.0, frac=3000.0 / 8000.0)
+    assert bench.roofline_of(low, issue) is low
+    only_adds = bench.issue_rates(None, 200.0, 1.3e8)
+    assert bench.roofline_of(hbm, only_adds)["frac"] == only_adds["scatter_adds"]["frac"]
+
+
 def test_rejection_cap_refused_on_the_host():
     """Stratified rejection whose first batch plus the device refill cap
     (2^22 candidates) cannot cover q omega / zeta plus eight standard
