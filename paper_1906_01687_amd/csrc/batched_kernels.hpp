@@ -25,7 +25,11 @@ __device__ __forceinline__ void flush_lds(const LT* lds, int64_t n, double* __re
 }
 
 template <int D, typename FT, typename VT>
-__global__ __launch_bounds__(1024) void batched_grad_kernel(BatchGradArgs ba) {
+// The problem table is its own read-only, non-aliased argument: its fields are
+// then read with scalar loads through the scalar cache and kept across a
+// unit's items, instead of vector loads repeated for every item (device
+// atomics in the loop could otherwise alias it).
+__global__ __launch_bounds__(1024) void batched_grad_kernel(BatchGradArgs ba, const GradArgs* __restrict__ probs) {
     using T = typename Compute<FT>::type;
     extern __shared__ double lds[];
     // this wave's 64 sample records, after the largest partial
@@ -42,7 +46,7 @@ __global__ __launch_bounds__(1024) void batched_grad_kernel(BatchGradArgs ba) {
     int32_t prev = -1;
     for (int64_t u = ba.block_ptr[blockIdx.x]; u < u_end; ++u) {
         const BatchUnit un = ba.units[u];
-        const GradArgs& a = ba.probs[un.problem];
+        const GradArgs& a = probs[un.problem];
         const bool f32 = ba.lds_fp32[un.problem] != 0;
         const int64_t n = a.lds_total;
         // a workgroup's units are sorted by problem: the partial is cleared when
@@ -95,9 +99,9 @@ void batched_grad_launch(const BatchLaunch& bl, const BatchGradArgs& ba, hipStre
     auto go = [&](auto kernel) {
         allow_full_lds(reinterpret_cast<const void*>(kernel));
         if (e0 || e1)
-            hipExtLaunchKernelGGL(kernel, g, t, (std::uint32_t)bl.lds_bytes, s, e0, e1, 0u, ba);
+            hipExtLaunchKernelGGL(kernel, g, t, (std::uint32_t)bl.lds_bytes, s, e0, e1, 0u, ba, ba.probs);
         else
-            hipLaunchKernelGGL(kernel, g, t, bl.lds_bytes, s, ba);
+            hipLaunchKernelGGL(kernel, g, t, bl.lds_bytes, s, ba, ba.probs);
     };
     if (bl.fdtype == GCP_F64) {
         if (bl.vdtype == GCP_F64) go(batched_grad_kernel<D, double, double>);
