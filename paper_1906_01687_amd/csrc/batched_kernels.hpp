@@ -20,7 +20,7 @@ template <typename LT>
 __device__ __forceinline__ void flush_lds(const LT* lds, int64_t n, double* __restrict__ acc) {
     for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
         const LT v = lds[e];
-        if (v != LT(0)) unsafeAtomicAdd(&acc[e], (double)v);
+        if (v != LT(0)) gadd(acc + e, (double)v);
     }
 }
 

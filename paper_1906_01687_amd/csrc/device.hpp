@@ -125,6 +125,23 @@ __host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
     return z ^ (z >> 31);
 }
 
+// Loads and atomic adds through global-address-space pointers.  A pointer
+// read from memory (a field of a problem record in device memory) is generic,
+// and a generic (flat) memory instruction counts against the LDS counter as
+// well as the vector-memory one, so a later wait for an LDS result would also
+// wait for it (a gather in flight, or a device atomic).
+template <typename V>
+__device__ __forceinline__ V gld(const V* p) {
+    return *(const __attribute__((address_space(1))) V*)p;
+}
+template <typename V>
+__device__ __forceinline__ void gadd(V* p, V v) {
+    auto g = (__attribute__((address_space(1))) V*)p;
+    [[clang::atomic(ignore_denormal_mode)]] {
+        (void)__hip_atomic_fetch_add(g, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 struct NzTable {
     const uint64_t* keys;
     const uint32_t* pos;
@@ -137,8 +154,8 @@ __device__ __forceinline__ int64_t nz_find(const NzTable& t, uint64_t L) {
     const uint64_t want = L + 1;
     uint64_t h = mix64(L) & t.mask;
     for (uint64_t probe = 0; probe <= t.mask; ++probe) {
-        const uint64_t k = t.keys[h];
-        if (k == want) return (int64_t)t.pos[h];
+        const uint64_t k = gld(t.keys + h);
+        if (k == want) return (int64_t)gld(t.pos + h);
         if (k == 0) return -1;
         h = (h + 1) & t.mask;
     }
@@ -148,14 +165,14 @@ __device__ __forceinline__ int64_t nz_find(const NzTable& t, uint64_t L) {
 // COO position of linear key L, or -1: the bitmap (when present) answers
 // "not stored" with one load, so only stored entries walk the hash.
 __device__ __forceinline__ int64_t nz_lookup(const NzTable& t, uint64_t L) {
-    if (t.bitmap && !((t.bitmap[L >> 5] >> (L & 31)) & 1u)) return -1;
+    if (t.bitmap && !((gld(t.bitmap + (L >> 5)) >> (L & 31)) & 1u)) return -1;
     return nz_find(t, L);
 }
 
 // Whether X is nonzero at linear key L: one bitmap load when the bitmap
 // exists, else the hash probe sequence.
 __device__ __forceinline__ bool nz_member(const NzTable& t, uint64_t L) {
-    if (t.bitmap) return (t.bitmap[L >> 5] >> (L & 31)) & 1u;
+    if (t.bitmap) return (gld(t.bitmap + (L >> 5)) >> (L & 31)) & 1u;
     return nz_find(t, L) >= 0;
 }
 

@@ -118,20 +118,20 @@ __device__ __forceinline__ void produce(const GradArgs& a, uint64_t iter, int64_
             L = linear_key<D>(i, a.dims.n);
         }
         if (a.format == GCP_DENSE) {
-            x = (T)vals[L];
-            if (wts) ew = (T)wts[L];
+            x = (T)gld(vals + L);
+            if (wts) ew = (T)gld(wts + L);
         } else {
             const int64_t e = nz_lookup(a.tab, L);
-            x = e >= 0 ? (T)vals[e] : T(0);
-            if (wts) ew = e >= 0 ? (T)wts[e] : (T)a.w_zero;
+            x = e >= 0 ? (T)gld(vals + e) : T(0);
+            if (wts) ew = e >= 0 ? (T)gld(wts + e) : (T)a.w_zero;
         }
         code = GCP_STRATUM_UNIFORM;
     } else if (c < a.p) {
         const uint64_t e = draw_nonzero(a.seed, a.pid, (uint64_t)c, iter, (uint64_t)a.nnz);
 #pragma unroll
-        for (int k = 0; k < D; ++k) i[k] = a.coo[e * D + k];
-        x = (T)vals[e];
-        if (wts) ew = (T)wts[e];
+        for (int k = 0; k < D; ++k) i[k] = gld(a.coo + e * D + k);
+        x = (T)gld(vals + e);
+        if (wts) ew = (T)gld(wts + e);
         code = a.sampler == GCP_SAMPLER_SEMI_STRATIFIED ? GCP_STRATUM_NZ_CORR : GCP_STRATUM_NZ;
     } else {
         draw_index<D>(a.seed, a.pid, (uint64_t)(c - a.p), iter, kPurposeUniform, a.dims.n, i);
@@ -486,9 +486,9 @@ __device__ __forceinline__ void pass_batches(const GradArgs& a, const PhaseB<D, 
                                                           ((lrow + cc * (uint32_t)sizeof(LT)) ^ hs)),
                                     (LT)v);
                         else if (b.acc32)
-                            unsafeAtomicAdd(static_cast<float*>(b.accj[k]) + (row + cc), (float)v);
+                            gadd(static_cast<float*>(b.accj[k]) + (row + cc), (float)v);
                         else
-                            unsafeAtomicAdd(static_cast<double*>(b.accj[k]) + (row + cc), (double)v);
+                            gadd(static_cast<double*>(b.accj[k]) + (row + cc), (double)v);
                     }
                 }
             }

@@ -161,7 +161,7 @@ __global__ __launch_bounds__(1024) void grad_kernel(GradArgs a) {
         if (a.loss_sum) {
             double f = (double)fsum;
             for (int o = kWave / 2; o > 0; o >>= 1) f += __shfl_xor(f, o);
-            if (lane == 0 && f != 0.0) unsafeAtomicAdd(a.loss_sum, f);
+            if (lane == 0 && f != 0.0) gadd(a.loss_sum, f);
         }
     }
     __syncthreads();
@@ -323,7 +323,7 @@ __global__ __launch_bounds__(256) void loss_grad_kernel(LossArgs a) {
     if (a.loss_sum) {
         double f = (double)fsum;
         for (int o = kWave / 2; o > 0; o >>= 1) f += __shfl_xor(f, o);
-        if (lane == 0 && f != 0.0) unsafeAtomicAdd(a.loss_sum, f);
+        if (lane == 0 && f != 0.0) gadd(a.loss_sum, f);
     }
 }
 
