@@ -70,8 +70,14 @@ __device__ __forceinline__ Sample<D, typename Compute<FT>::type> item_sample(con
 #pragma unroll
         for (int k = 0; k < D; ++k) i[k] = a.zstage[((int64_t)chunk * kWave + lane) * D + k];
         const uint32_t cnt = a.chunk_count[chunk];
-        const uint64_t rank = chunk_prefix(a, chunk) + (uint64_t)lane;
-        if ((uint32_t)lane < cnt && rank < (uint64_t)a.q) smp = make_sample<D, T>(a, i, T(0), GCP_STRATUM_ZERO);
+        // the earlier chunks accepted at most 64 each, so the rank of this
+        // chunk's accepted candidate l is at most 64 chunk + l: a chunk with
+        // 64 chunk + 63 < q lies wholly within the first q zeros and needs no
+        // prefix (in practice all but the last few chunks)
+        const bool all_in = (uint64_t)chunk * kWave + (kWave - 1) < (uint64_t)a.q;
+        const uint64_t rank = all_in ? 0 : chunk_prefix(a, chunk) + (uint64_t)lane;
+        if ((uint32_t)lane < cnt && (all_in || rank < (uint64_t)a.q))
+            smp = make_sample<D, T>(a, i, T(0), GCP_STRATUM_ZERO);
     }
     return smp;
 }
