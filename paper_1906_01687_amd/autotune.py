@@ -64,10 +64,13 @@ def _time_candidate(problems: Sequence[Problem], tune, steps: int, warmup: int) 
 
 def tune_batch(problems: Sequence[Problem], candidates: Optional[Iterable[Tuple[int, ...]]] = None,
                steps: int = 10, warmup: int = 2, cache_path: Optional[str] = DEFAULT_CACHE,
-               verbose: bool = False) -> Tuple[Tuple[int, ...], Dict[str, float]]:
+               verbose: bool = False, finalists: int = 4) -> Tuple[Tuple[int, ...], Dict[str, float]]:
     """Best (threads, unit_items, schedule, cols_per_lane) for this batch and the timings (ms)
     of all candidates; a cached answer for the same signature is returned
-    untimed."""
+    untimed.  The `finalists` fastest candidates of the first round are timed
+    again over three times as many steps and the best of that round is kept:
+    shapes within a few percent of each other are otherwise told apart by a
+    few launches (their timings then are those of the second round)."""
     sig = signature(problems)
     cache = {}
     if cache_path and os.path.exists(cache_path):
@@ -81,7 +84,8 @@ def tune_batch(problems: Sequence[Problem], candidates: Optional[Iterable[Tuple[
         return tuple(entry["best"]), entry.get("times", {})
     times: Dict[str, float] = {}
     best, best_ms = None, float("inf")
-    for tune in (candidates or DEFAULT_CANDIDATES):
+    cands = [tuple(t) for t in (candidates or DEFAULT_CANDIDATES)]
+    for tune in cands:
         ms = _time_candidate(problems, tune, steps, warmup)
         times["x".join(str(v) for v in tune)] = ms
         if verbose:
@@ -90,6 +94,17 @@ def tune_batch(problems: Sequence[Problem], candidates: Optional[Iterable[Tuple[
                   f"{ms * 1e3:.1f} us", file=sys.stderr, flush=True)
         if ms < best_ms:
             best, best_ms = tuple(tune), ms
+    keys = {"x".join(str(v) for v in t): t for t in cands}
+    ranked = sorted(times, key=times.get)[:max(1, finalists)]
+    if len(ranked) > 1:
+        best, best_ms = None, float("inf")
+        for key in ranked:
+            ms = _time_candidate(problems, keys[key], 3 * steps, warmup)
+            times[key] = ms
+            if verbose:
+                print(f"[autotune] finalist {key}: {ms * 1e3:.1f} us", file=sys.stderr, flush=True)
+            if ms < best_ms:
+                best, best_ms = keys[key], ms
     if cache_path:
         cache[sig] = {"best": list(best), "times": times}
         os.makedirs(os.path.dirname(cache_path), exist_ok=True)
