@@ -38,8 +38,9 @@ constexpr int64_t kSampleFixedCost = 19;
 
 // What the reduction needs per problem.
 struct BatchReduceProblem {
-    int64_t flat_off;  // first element of the problem in the concatenated accumulator
-    int64_t P;         // sum_k n_k r
+    int64_t flat_off;     // first element of the problem in the concatenated accumulator
+    int64_t P;            // sum_k n_k r
+    int64_t first_block;  // the problem's first reduction workgroup
     void* A;
     float* A_master;
     void* B;
@@ -49,12 +50,9 @@ struct BatchReduceProblem {
 };
 
 struct BatchReduceArgs {
-    const BatchReduceProblem* probs;
-    const int64_t* flat_off;  // [count + 1]
-    int32_t count;
     int adam;
     double* acc;
-    int64_t P_all;
+    int64_t nblk;  // reduction workgroups of all problems (entries of the block table)
     int64_t* state;
     uint64_t* bump_counter;
     double alpha, beta1, beta2, eps;
@@ -62,8 +60,18 @@ struct BatchReduceArgs {
 };
 
 
+constexpr int kBatchRedThreads = 256;
+
+// Each block of the table covers kBatchRedThreads consecutive elements of one
+// problem (a problem gets ceil(P / kBatchRedThreads) blocks), so the problem and
+// its record are read with uniform loads through the scalar cache, ahead of the
+// element loads, instead of a search over the problem offsets per element.  The
+// tables are read-only, non-aliased kernel arguments for that reason.  A
+// workgroup takes every gridDim.x-th block (one, unless the table is longer
+// than the grid).
 template <typename T, int ADAM>
-__global__ __launch_bounds__(256) void batched_reduce_kernel(BatchReduceArgs r) {
+__global__ __launch_bounds__(kBatchRedThreads) void batched_reduce_kernel(
+    BatchReduceArgs r, const BatchReduceProblem* __restrict__ probs, const int32_t* __restrict__ blk_prob) {
     __shared__ double bc[2];
     if (r.bump_counter && blockIdx.x == 0 && threadIdx.x == 0) r.bump_counter[0] += 1;
     if (ADAM && threadIdx.x == 0) {
@@ -72,17 +80,11 @@ __global__ __launch_bounds__(256) void batched_reduce_kernel(BatchReduceArgs r) 
         bc[1] = 1.0 - pow(r.beta2, t);
     }
     __syncthreads();
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < r.P_all;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        // problem of element e: last b with flat_off[b] <= e
-        int lo = 0, hi = r.count - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (r.flat_off[mid] <= e) lo = mid;
-            else hi = mid - 1;
-        }
-        const BatchReduceProblem& pb = r.probs[lo];
-        const int64_t local = e - pb.flat_off;
+    for (int64_t j = blockIdx.x; j < r.nblk; j += gridDim.x) {
+        const BatchReduceProblem& pb = probs[blk_prob[j]];
+        const int64_t local = (j - pb.first_block) * kBatchRedThreads + threadIdx.x;
+        if (local >= pb.P) continue;
+        const int64_t e = pb.flat_off + local;
         const double g = r.acc[e];
         r.acc[e] = 0.0;  // cleared for the next step
         if (pb.G) static_cast<T*>(pb.G)[local] = (T)g;
@@ -135,13 +137,14 @@ struct gcp_batch {
     std::vector<uint8_t> lds_fp32;
     std::vector<BatchReduceProblem> red;
     std::vector<int64_t> flat_off;
+    std::vector<int32_t> red_blk;  // problem of each reduction workgroup
     int threads = 1024;
     int64_t blocks = 1;
     size_t lds_bytes = 0;
     uint32_t stage_off = 0;
     int64_t P_all = 0;
     // workspace layout
-    size_t off_args = 0, off_units = 0, off_bptr = 0, off_f32 = 0, off_red = 0, off_flat = 0, off_acc = 0;
+    size_t off_args = 0, off_units = 0, off_bptr = 0, off_f32 = 0, off_red = 0, off_rblk = 0, off_acc = 0;
     size_t ws_bytes = 0;
     char* ws = nullptr;
     // graph of captured steps (gcp_batched_graph_capture) and the stream it
@@ -258,6 +261,8 @@ gcp_status batch_create(const gcp_problem* problems, int32_t count, const gcp_ba
         BatchReduceProblem rp{};
         rp.flat_off = flat;
         rp.P = P;
+        rp.first_block = (int64_t)B->red_blk.size();
+        B->red_blk.insert(B->red_blk.end(), (size_t)((P + kBatchRedThreads - 1) / kBatchRedThreads), b);
         rp.A = pr.A;
         rp.A_master = pr.A_master;
         rp.B = pr.B;
@@ -373,7 +378,7 @@ gcp_status batch_create(const gcp_problem* problems, int32_t count, const gcp_ba
     B->off_bptr = place(sizeof(int64_t) * ((size_t)blocks + 1));
     B->off_f32 = place((size_t)count);
     B->off_red = place(sizeof(BatchReduceProblem) * (size_t)count);
-    B->off_flat = place(sizeof(int64_t) * ((size_t)count + 1));
+    B->off_rblk = place(sizeof(int32_t) * B->red_blk.size());
     B->off_acc = place(sizeof(double) * (size_t)std::max<int64_t>(1, flat));
     B->ws_bytes = (off + 255) & ~size_t(255);
     *out = B;
@@ -401,7 +406,7 @@ gcp_status batch_prepare(gcp_batch* B, void* ws, size_t ws_bytes, hipStream_t s)
         {B->off_bptr, B->block_ptr.data(), sizeof(int64_t) * B->block_ptr.size()},
         {B->off_f32, B->lds_fp32.data(), B->lds_fp32.size()},
         {B->off_red, B->red.data(), sizeof(BatchReduceProblem) * B->red.size()},
-        {B->off_flat, B->flat_off.data(), sizeof(int64_t) * B->flat_off.size()},
+        {B->off_rblk, B->red_blk.data(), sizeof(int32_t) * B->red_blk.size()},
     };
     // the tables are small and this is set-up, not the hot path: copy synchronously
     if (hipStreamSynchronize(s) != hipSuccess) return set_error(GCP_ERR_HIP, "hipStreamSynchronize failed");
@@ -432,11 +437,10 @@ gcp_status batch_step(gcp_batch* B, const AdamParams* adam, uint64_t* iteration_
     dispatch_d(B->d, [&](auto dc) { batched_grad_launch<decltype(dc)::value>(bl, ba, s, e0, e1); });
     if (gcp_status st = check_launch("gcp_batched step (gradient)")) return st;
     BatchReduceArgs r{};
-    r.probs = reinterpret_cast<const BatchReduceProblem*>(base + B->off_red);
-    r.flat_off = reinterpret_cast<const int64_t*>(base + B->off_flat);
-    r.count = B->count;
+    const auto* rprobs = reinterpret_cast<const BatchReduceProblem*>(base + B->off_red);
+    const auto* rblk = reinterpret_cast<const int32_t*>(base + B->off_rblk);
     r.acc = reinterpret_cast<double*>(base + B->off_acc);
-    r.P_all = B->P_all;
+    r.nblk = (int64_t)B->red_blk.size();
     r.bump_counter = iteration_counter;
     if (adam) {
         r.adam = 1;
@@ -447,17 +451,16 @@ gcp_status batch_step(gcp_batch* B, const AdamParams* adam, uint64_t* iteration_
         r.eps = adam->eps;
         r.eps_mode = adam->eps_mode;
     }
-    const int64_t nb = std::max<int64_t>(1, std::min<int64_t>(8192, (B->P_all + 255) / 256));
-    const dim3 g((unsigned)nb), t(256);
+    const dim3 g((unsigned)std::min<int64_t>(65536, r.nblk)), t(kBatchRedThreads);
     if (!adam) {
-        if (B->fdtype == GCP_F64) hipLaunchKernelGGL((batched_reduce_kernel<double, 0>), g, t, 0, s, r);
-        else hipLaunchKernelGGL((batched_reduce_kernel<float, 0>), g, t, 0, s, r);
+        if (B->fdtype == GCP_F64) hipLaunchKernelGGL((batched_reduce_kernel<double, 0>), g, t, 0, s, r, rprobs, rblk);
+        else hipLaunchKernelGGL((batched_reduce_kernel<float, 0>), g, t, 0, s, r, rprobs, rblk);
     } else if (B->fdtype == GCP_F64) {
-        hipLaunchKernelGGL((batched_reduce_kernel<double, 1>), g, t, 0, s, r);
+        hipLaunchKernelGGL((batched_reduce_kernel<double, 1>), g, t, 0, s, r, rprobs, rblk);
     } else if (B->fdtype == GCP_F32) {
-        hipLaunchKernelGGL((batched_reduce_kernel<float, 1>), g, t, 0, s, r);
+        hipLaunchKernelGGL((batched_reduce_kernel<float, 1>), g, t, 0, s, r, rprobs, rblk);
     } else {
-        hipLaunchKernelGGL((batched_reduce_kernel<float, 2>), g, t, 0, s, r);
+        hipLaunchKernelGGL((batched_reduce_kernel<float, 2>), g, t, 0, s, r, rprobs, rblk);
     }
     return check_launch("gcp_batched step (reduction)");
 }
