@@ -110,11 +110,15 @@ def test_batched_fp64():
     batch.close()
 
 
-def test_batched_adam_matches_single_problem_steps():
-    announce("batched Adam steps vs single-problem gcp_sampled_adam_step")
-    ws = mixed_workloads()
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_batched_adam_matches_single_problem_steps(dtype):
+    """BF16 factors: the Adam step updates the float master copy and rounds it
+    to the BF16 factors; the master copies are compared."""
+    announce(f"batched Adam steps vs single-problem gcp_sampled_adam_step, {dtype}")
+    ws = mixed_workloads(dtype=dtype)
     pa = [make_problem(w, b) for b, w in enumerate(ws)]
     pb = [make_problem(w, b) for b, w in enumerate(ws)]
+    params = (lambda p: p.M.master) if dtype == "bf16" else (lambda p: p.M.flat)
     batch = gcp.Batch(pa)
     singles = []
     for b, (w, p) in enumerate(zip(ws, pb)):
@@ -122,16 +126,18 @@ def test_batched_adam_matches_single_problem_steps():
         cfg = gcp.sampling(w.sampler, s=w.s, p=w.p, q=w.q, seed=w.seed, problem_id=b)
         singles.append((gcp.SampledAdamStep(w.loss, p.X, p.M, cfg, adam), adam))
     for it in range(3):
-        before = [p.M.flat.to(torch.float64).clone() for p in pb]
+        before = [params(p).to(torch.float64).clone() for p in pb]
         batch.adam_step(lr=0.01)
         for step, _ in singles:
             step(iteration=it)
         torch.cuda.synchronize()
         assert int(batch.state[0]) == it + 1
         for b in range(len(ws)):
-            xa, xb = pa[b].M.flat.to(torch.float64), pb[b].M.flat.to(torch.float64)
+            xa, xb = params(pa[b]).to(torch.float64), params(pb[b]).to(torch.float64)
             err = float((xa - xb).norm() / (xb - before[b]).norm().clamp_min(1e-30))
             assert err <= 1e-5, (b, it, err)
+            if dtype == "bf16":  # the factors are the master copy rounded to BF16
+                assert torch.equal(pa[b].M.flat, pa[b].M.master.to(torch.bfloat16)), (b, it)
     batch.close()
 
 
