@@ -110,10 +110,11 @@ def test_batched_fp64():
     batch.close()
 
 
-@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("dtype", ["f32", "f64", "bf16"])
 def test_batched_adam_matches_single_problem_steps(dtype):
     """BF16 factors: the Adam step updates the float master copy and rounds it
-    to the BF16 factors; the master copies are compared."""
+    to the BF16 factors; the master copies are compared.  FP64: the two
+    gradients differ only in the order of FP64 additions, hence 1e-10."""
     announce(f"batched Adam steps vs single-problem gcp_sampled_adam_step, {dtype}")
     ws = mixed_workloads(dtype=dtype)
     pa = [make_problem(w, b) for b, w in enumerate(ws)]
@@ -135,7 +136,7 @@ def test_batched_adam_matches_single_problem_steps(dtype):
         for b in range(len(ws)):
             xa, xb = params(pa[b]).to(torch.float64), params(pb[b]).to(torch.float64)
             err = float((xa - xb).norm() / (xb - before[b]).norm().clamp_min(1e-30))
-            assert err <= 1e-5, (b, it, err)
+            assert err <= (1e-10 if dtype == "f64" else 1e-5), (b, it, err)
             if dtype == "bf16":  # the factors are the master copy rounded to BF16
                 assert torch.equal(pa[b].M.flat, pa[b].M.master.to(torch.bfloat16)), (b, it)
     batch.close()
