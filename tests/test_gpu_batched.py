@@ -197,6 +197,40 @@ def test_library_graph_replay_equals_eager_steps():
     bb.close()
 
 
+def test_batched_reduction_table_longer_than_its_grid():
+    """A batch whose reduction has more blocks of 256 parameters than the
+    reduction grid holds (65536): (600000 + 2 + 2) x 32 parameters make 75001
+    blocks, so some workgroups take two.  Adam steps against the
+    single-problem calls."""
+    announce("batched: reduction block table longer than the grid")
+    specs = [((600_000, 2, 2), 32, 20_000), ((23, 23, 23), 7, 400)]
+    ws = []
+    for b, (dims, r, s_) in enumerate(specs):
+        X, A0, _ = synth.dense_problem(dims, r, synth.GAUSSIAN, seed=970 + b)
+        ws.append(synth.Workload(f"long{b}", dims, r, synth.GAUSSIAN, synth.UNIFORM, "f32", s=s_, dense=X,
+                                 A_init=A0, seed=80))
+    assert (600_004 * 32 + 255) // 256 > 65536
+    pa = [make_problem(w, b) for b, w in enumerate(ws)]
+    pb = [make_problem(w, b) for b, w in enumerate(ws)]
+    batch = gcp.Batch(pa)
+    singles = []
+    for b, (w, p) in enumerate(zip(ws, pb)):
+        adam = gcp.Adam(p.M, lr=0.01, lower=w.lower)
+        cfg = gcp.sampling(w.sampler, s=w.s, seed=w.seed, problem_id=b)
+        singles.append(gcp.SampledAdamStep(w.loss, p.X, p.M, cfg, adam))
+    for it in range(2):
+        before = [p.M.flat.to(torch.float64).clone() for p in pb]
+        batch.adam_step(lr=0.01)
+        for step in singles:
+            step(iteration=it)
+        torch.cuda.synchronize()
+        for b in range(len(ws)):
+            xa, xb = pa[b].M.flat.to(torch.float64), pb[b].M.flat.to(torch.float64)
+            err = float((xa - xb).norm() / (xb - before[b]).norm().clamp_min(1e-30))
+            assert err <= 1e-5, (b, it, err)
+    batch.close()
+
+
 def test_batched_large_problems_use_fp32_lds_and_atomics():
     announce("batched: problems beyond the FP64 LDS budget (FP32 LDS, device atomics)")
     # (700+20+15) x 32: 188 KB in FP64 -> FP32 LDS; (1500+35) x 32: 196 KB even in FP32 -> atomics
