@@ -98,6 +98,36 @@ def test_batched_grad_matches_single_problem_calls(tune):
     batch.close()
 
 
+@pytest.mark.parametrize("cpl", [0, 2])
+def test_batched_high_ranks(cpl):
+    """Ranks 64-256 (two or four rank columns per lane, 32 or 64 lanes per
+    sample) in one FP32 batch, with the automatic layout and with two columns
+    per lane asked for (rank 256 falls back to four): every problem against
+    its single-problem call and the oracle."""
+    announce(f"batched gradient, ranks 64-256, cols_per_lane={cpl}")
+    specs = [(11, 64, 0), (9, 100, 1), (8, 256, 0), (13, 130, 2), (10, 17, 1)]
+    losses = [synth.GAUSSIAN, synth.POISSON, synth.BERNOULLI_ODDS]
+    ws = []
+    for b, (n, r, loss) in enumerate(specs):
+        X, A0, lower = synth.dense_problem((n, n + 1, n + 2), r, losses[loss], seed=980 + b,
+                                           density=0.05 if loss else None)
+        ws.append(synth.Workload(f"hr{b}", (n, n + 1, n + 2), r, losses[loss], synth.UNIFORM, "f32",
+                                 s=max(64, n ** 3 // 4), dense=X, A_init=A0, seed=81, lower=lower))
+    probs = [make_problem(w, b) for b, w in enumerate(ws)]
+    batch = gcp.Batch(probs, tune=(1024, 0, gcp.BATCH_CONTIGUOUS, cpl) if cpl else None)
+    batch.grad()
+    torch.cuda.synchronize()
+    for b, (w, p) in enumerate(zip(ws, probs)):
+        cfg = gcp.sampling(w.sampler, s=w.s, seed=w.seed, problem_id=b)
+        single = gcp.sampled_grad(w.loss, p.X, p.M, cfg)
+        torch.cuda.synchronize()
+        Gb = p.M.grad_views(p.G)
+        err = max(rel_fro(Gb, [s_.detach().to(torch.float64).cpu().numpy() for s_ in single]))
+        assert err <= 1e-5, (b, err)
+        check_grad(Gb, *oracle_gradient(w, b, 0, "f32"), 1e-5, f"batched rank {w.rank}")
+    batch.close()
+
+
 def test_batched_fp64():
     announce("batched gradient, FP64 factors")
     ws = mixed_workloads(dtype="f64")[:5]
