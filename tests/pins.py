@@ -47,8 +47,12 @@ def numpy_index(seed, pid, j, iteration, purpose, dims):
     return tuple(out)
 
 
-def khatri_rao(mats):
-    """Column-wise Kronecker product; the first matrix varies slowest."""
+def khatri_rao(mats, r=None):
+    """Column-wise Kronecker product; the first matrix varies slowest.  The
+    product of no matrices is the 1 x r row of ones (a one-way model has
+    m_i = sum_j a_ij, so its leave-one-out factor is 1)."""
+    if not mats:
+        return np.ones((1, r))
     out = mats[0]
     for m in mats[1:]:
         out = (out[:, None, :] * m[None, :, :]).reshape(-1, out.shape[1])
@@ -76,7 +80,7 @@ def exact_gradient(loss, X, A, eps=oracle.LOSS_EPS, W=None):
         Y = Y * W
     G = []
     for k in range(len(A)):
-        Z = khatri_rao([A[j] for j in range(len(A)) if j != k])
+        Z = khatri_rao([A[j] for j in range(len(A)) if j != k], A[k].shape[1])
         G.append(unfold(Y, k) @ Z)
     return G
 
@@ -250,7 +254,7 @@ def pin_index_uniformity(seed=1234):
 def pin_enumeration_equals_unfolding(losses=(oracle.GAUSSIAN, oracle.BERNOULLI_ODDS, oracle.POISSON)):
     """P1: the sampled gradient over every index once (weight omega/s = 1) equals
     Y_(k) Z_k computed by explicit unfolding and Khatri-Rao products (eq. Gk)."""
-    for dims in [(3, 4, 5), (2, 3, 4, 5)]:
+    for dims in [(3, 4, 5), (2, 3, 4, 5), (7,), (3, 4), (2, 3, 2, 3, 2)]:
         for loss in losses:
             if loss == oracle.GAUSSIAN:
                 X, A = tiny_dense(dims)
