@@ -128,6 +128,38 @@ def test_batched_high_ranks(cpl):
     batch.close()
 
 
+@pytest.mark.parametrize("dims_list", [[(37,), (120,)], [(30, 20), (9, 41), (50, 3)],
+                                       [(7, 8, 9, 10), (5, 12, 6, 9)], [(4, 5, 6, 3, 7), (6, 3, 5, 4, 4)]],
+                         ids=["d1", "d2", "d4", "d5"])
+def test_batched_other_tensor_orders(dims_list):
+    """Batches of 1-, 2-, 4- and 5-way dense problems (one order per batch):
+    every problem against its single-problem call and the oracle."""
+    d = len(dims_list[0])
+    announce(f"batched gradient, {d}-way problems")
+    losses = [synth.GAUSSIAN, synth.POISSON, synth.BERNOULLI_ODDS]
+    ws = []
+    for b, dims in enumerate(dims_list):
+        loss = losses[b % 3]
+        r = [3, 8, 5][b % 3]
+        X, A0, lower = synth.dense_problem(dims, r, loss, seed=990 + 10 * d + b,
+                                           density=0.1 if loss != synth.GAUSSIAN else None)
+        ws.append(synth.Workload(f"o{d}_{b}", dims, r, loss, synth.UNIFORM, "f32",
+                                 s=max(50, math.prod(dims) // 3), dense=X, A_init=A0, seed=82, lower=lower))
+    probs = [make_problem(w, b) for b, w in enumerate(ws)]
+    batch = gcp.Batch(probs)
+    batch.grad()
+    torch.cuda.synchronize()
+    for b, (w, p) in enumerate(zip(ws, probs)):
+        cfg = gcp.sampling(w.sampler, s=w.s, seed=w.seed, problem_id=b)
+        single = gcp.sampled_grad(w.loss, p.X, p.M, cfg)
+        torch.cuda.synchronize()
+        Gb = p.M.grad_views(p.G)
+        err = max(rel_fro(Gb, [s_.detach().to(torch.float64).cpu().numpy() for s_ in single]))
+        assert err <= 1e-5, (b, err)
+        check_grad(Gb, *oracle_gradient(w, b, 0, "f32"), 1e-5, f"batched {d}-way problem {b}")
+    batch.close()
+
+
 def test_batched_fp64():
     announce("batched gradient, FP64 factors")
     ws = mixed_workloads(dtype="f64")[:5]

@@ -152,6 +152,12 @@ CASES = [
     ("counts_semi_r64_d4", lambda: small_sparse("counts", dims=(30, 7, 11, 13), rank=64)),
     ("dense_f32_d5_r16", lambda: small_dense(dims=(7, 3, 4, 6, 5), rank=16, s=1111)),
     ("dense_f64_d2_r2", lambda: small_dense(dims=(40, 31), rank=2, s=777, dtype="f64")),
+    # one mode (the leave-one-out product is empty: every column of a row gets
+    # the same w g) and six and eight modes
+    ("dense_f32_d1_r6", lambda: small_dense(dims=(300,), rank=6, s=500)),
+    ("dense_f64_d1_poisson_r5", lambda: small_dense(dims=(900,), rank=5, s=700, dtype="f64", loss=synth.POISSON)),
+    ("dense_f32_d6_r9", lambda: small_dense(dims=(4, 3, 5, 2, 3, 4), rank=9, s=1500)),
+    ("dense_f64_d8_r3", lambda: small_dense(dims=(3, 2, 4, 2, 3, 2, 2, 3), rank=3, s=900, dtype="f64")),
     ("dense_f32_gamma_r6", lambda: small_dense(rank=6, loss=synth.GAMMA)),
     ("dense_f64_beta_r4", lambda: small_dense(rank=4, loss=synth.BETA_HALF, dtype="f64")),
     ("counts_semi_beta_r10", lambda: small_sparse("counts", rank=10, loss=synth.BETA_HALF)),
